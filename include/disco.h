@@ -1,0 +1,185 @@
+/*
+ * libdisco: C ABI of the MI355X (gfx950) implementation of the hot path of the
+ * subtraction method for disconnected diagrams ("Subtraction method for
+ * disconnected diagrams in full QCD", Barca, Crawford, Finkenrath, Schaefer,
+ * Urrea-Nino).
+ *
+ * The path: the Wilson-clover operator D and its domain-restricted form
+ * D_Lambda (hops across domain faces removed) are inverted on distillation
+ * sources; the solutions are projected as V^+ D^-1 V (perambulators); the
+ * Gamma-traced quark loops per timeslice give the full, completely factorised
+ * and subtracted disconnected correlators.
+ *
+ * General rules
+ *   - Every function returns an int: DISCO_OK (0) or a negative DISCO_E* code.
+ *     disco_last_error(ctx) returns a message for the last failure on ctx.
+ *     No C++ exception or abort crosses this interface.
+ *   - The caller owns every buffer it passes.  "device" pointers must point to
+ *     memory on the context's GPU (hipMalloc or a torch tensor); "host"
+ *     pointers to ordinary host memory.  Each argument says which.
+ *   - The context owns its internal copies (links, clover term, smeared links,
+ *     workspaces) and frees them in disco_destroy.
+ *   - All GPU work is issued on the context's stream (disco_set_stream; the
+ *     default is the null stream).  Functions that return host results
+ *     synchronise that stream before returning; the others are asynchronous
+ *     with respect to the host unless stated.
+ *   - One context per host thread at a time.
+ *
+ * Boundary layouts (all complex numbers are (re, im) pairs of doubles)
+ *   site index   s = x + Lx*(y + Ly*(z + Lz*t)); mu = 0,1,2,3 is x,y,z,t
+ *   links        U[s][mu][a][b]                       complex128, SU(3)
+ *   spinor field psi[s][spin][colour]                 complex128, 12 per site
+ *   spinor block psi[r][s][spin][colour]              r = 0..nrhs-1
+ *   eigenvectors Vev[t][i][xs][c], xs = x + Lx*(y + Ly*z)
+ *   perambulator tau[t][j][beta][i][alpha]            sink (j,beta), source (i,alpha)
+ *   loops        L[g][t]                              g over the requested channels
+ *
+ * Conventions: Euclidean hermitian gamma matrices in the chiral basis,
+ *   gamma_k = [[0, -i s_k], [i s_k, 0]] (k = 1,2,3 for x,y,z),
+ *   gamma_4 = [[0, 1], [1, 0]] (time), gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4
+ *   = diag(1,1,-1,-1).
+ */
+#ifndef DISCO_H
+#define DISCO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct disco_ctx disco_ctx;
+typedef struct disco_domains disco_domains;
+
+enum {
+    DISCO_OK = 0,
+    DISCO_EINVAL = -1,     /* bad argument (sizes, pointers, non-SU(3) links, ...) */
+    DISCO_ENOMEM = -2,     /* device or host allocation failed */
+    DISCO_EHIP = -3,       /* a HIP runtime call failed */
+    DISCO_ENOCONV = -4,    /* solver did not reach the tolerance (stats still filled) */
+    DISCO_EBREAKDOWN = -5, /* Krylov breakdown and no fallback allowed */
+    DISCO_ESTATE = -6      /* call made before the state it needs (gauge, clover) */
+};
+
+/* arithmetic / storage precisions */
+enum { DISCO_F64 = 0, DISCO_F32 = 1, DISCO_BF16 = 2 };
+/* where a pointer lives */
+enum { DISCO_HOST = 0, DISCO_DEVICE = 1 };
+/* loop channels Gamma */
+enum { DISCO_G_1 = 0, DISCO_G_5 = 1, DISCO_G_X = 2, DISCO_G_Y = 3, DISCO_G_Z = 4 };
+/* solver methods */
+enum {
+    DISCO_CGNR_F64 = 0,    /* conjugate gradients on D^+ D, all FP64 (plain judge) */
+    DISCO_BICGSTAB_DC = 1  /* BiCGStab in inner_prec inside FP64 defect correction */
+};
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context for a dims[0..3] = (Lx,Ly,Lz,Lt) lattice on HIP device
+ * `device`.  bc[mu] = +1 (periodic) or -1 (antiperiodic) is the phase of a
+ * fermion hop that crosses the lattice wrap in direction mu.  Extents must be
+ * >= 1 and the volume < 2^31.  *out receives the context (caller frees it with
+ * disco_destroy). */
+int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out);
+int disco_destroy(disco_ctx* ctx);
+/* Issue all later work on `hip_stream` (a hipStream_t; NULL = null stream). */
+int disco_set_stream(disco_ctx* ctx, void* hip_stream);
+/* Message for the last error on ctx (never NULL; "" when none). */
+const char* disco_last_error(const disco_ctx* ctx);
+
+/* ---------------------------------------------------------------- gauge / clover setup
+ * Wilson-clover operator in hopping normalisation (the action named at the
+ * start of the paper's Results section):
+ *   D psi(x) = A(x) psi(x) - kappa sum_mu [ b (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                         + b (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *   A(x) = 1 + i csw kappa sum_{mu<nu} sigma_mu_nu Fhat_mu_nu(x),
+ *   Fhat = (Q - Q^+)/8 with Q the sum of the four plaquette leaves at x,
+ *   sigma_mu_nu = (i/2)[gamma_mu, gamma_nu], b the boundary phase of the hop. */
+
+/* Load links U (boundary layout, complex128, V*4*9 entries) from host
+ * (where = DISCO_HOST) or device memory.  Returns DISCO_EINVAL when a link is
+ * not SU(3) to 1e-12 (max |U U^+ - 1|, |det U - 1|).  Invalidates the clover
+ * term and the smeared links. */
+int disco_gauge_set(disco_ctx* ctx, const void* U, int where);
+/* Build A(x) from the current links (FP64 arithmetic; FP64 and FP32 copies
+ * kept).  ESTATE before disco_gauge_set. */
+int disco_clover_setup(disco_ctx* ctx, double kappa, double csw);
+/* Copy the FP64 clover term out as [V][12][12] complex128 (index spin*3+colour)
+ * into device memory `A_out` (for checks). */
+int disco_clover_get(disco_ctx* ctx, void* A_out);
+
+/* ---------------------------------------------------------------- domains
+ * A separable partition of the lattice into domains Lambda_i (Domain
+ * decomposition subsection).  cut[mu*lmax + x] = 1 (host, uint8) marks the
+ * face between x and x+1 (mod L_mu) in direction mu as a domain boundary;
+ * lmax >= max(dims).  All cuts zero gives a single domain. */
+int disco_domains_create(disco_ctx* ctx, const uint8_t* cut, int lmax, disco_domains** out);
+int disco_domains_destroy(disco_domains* dom);
+
+/* ---------------------------------------------------------------- operators
+ * out = D in (dagger = 0) or D^+ in = gamma_5 D gamma_5 in (dagger = 1) for nrhs
+ * spinor fields in the boundary layout (device, complex128, nrhs*V*12
+ * entries).  prec selects the arithmetic: DISCO_F64, DISCO_F32 (inputs
+ * rounded to FP32, FP32 accumulation) or DISCO_BF16 (inputs rounded to BF16
+ * storage, FP32 links and accumulation).  in and out must not overlap. */
+int disco_dirac_apply(disco_ctx* ctx, int prec, int dagger, int nrhs, const void* in, void* out);
+/* Same with the domain-restricted operator D_Lambda of the Domain
+ * decomposition subsection: D restricted to the fields inside each domain of
+ * `dom` (Dirichlet faces): every hop across a cut face is dropped, A(x) is
+ * unchanged. */
+int disco_dirac_block_apply(disco_ctx* ctx, const disco_domains* dom, int prec, int dagger, int nrhs,
+                            const void* in, void* out);
+
+/* Internal ("native") spinor layout, for callers that keep fields resident:
+ *   F64  : [r][12][V] complex double, plane k = spin*3 + colour
+ *   F32  : [r][6][V]  float4 = components (2p, 2p+1) as (re, im, re, im)
+ *   BF16 : [r][3][V]  16 bytes = components 4q..4q+3 as bf16 (re, im) pairs
+ * disco_native_bytes gives the size of an nrhs block. */
+long long disco_native_bytes(const disco_ctx* ctx, int prec, int nrhs);
+int disco_to_native(disco_ctx* ctx, int prec, int nrhs, const void* in_canonical, void* out_native);
+int disco_from_native(disco_ctx* ctx, int prec, int nrhs, const void* in_native, void* out_canonical);
+/* out_native = D in_native on native blocks (dom = NULL for the full operator). */
+int disco_dirac_apply_native(disco_ctx* ctx, const disco_domains* dom, int prec, int dagger, int nrhs,
+                             const void* in_native, void* out_native);
+
+/* ---------------------------------------------------------------- solver */
+typedef struct {
+    int method;        /* DISCO_CGNR_F64 or DISCO_BICGSTAB_DC */
+    double tol;        /* target true ||b - D x|| / ||b|| per right-hand side, FP64 */
+    int max_iter;      /* cap on inner iterations summed over outer cycles */
+    int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */
+    double inner_tol;  /* relative reduction asked of each inner solve (e.g. 1e-5) */
+    int rhs_block;     /* right-hand sides per batched launch; 0 = tuned default */
+    int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
+    int check_every;   /* iterations between host convergence checks (0 = default) */
+} disco_solver_params;
+
+typedef struct {
+    int iters;              /* inner Krylov iterations */
+    int outer_iters;        /* defect-correction cycles (1 for CGNR) */
+    int fallback_used;      /* 1 when the FP64 fallback ran */
+    int converged;          /* 1 when true_rel_residual <= tol */
+    double true_rel_residual; /* ||b - D x|| / ||b||, FP64, recomputed at the end */
+} disco_solver_stats;
+
+/* Solve D x = b (dom = NULL) or D_Lambda x = b for nrhs right-hand sides b
+ * (device, boundary layout complex128).  x (device, same layout) receives the
+ * solutions; stats (host, nrhs entries, may be NULL) per right-hand side.
+ * Returns DISCO_ENOCONV if any right-hand side misses tol. */
+int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params* p,
+                          int nrhs, const void* b, void* x, disco_solver_stats* stats);
+
+/* ---------------------------------------------------------------- profiling
+ * Per-kernel-family timing of launches made while profiling is on, measured
+ * with HIP events recorded on the context's stream around each launch.
+ * kernel: 0 = Wilson-clover stencil (any precision).  bytes = algorithmic
+ * bytes of those launches (each input/output spinor, the links and the clover
+ * term counted once per site). */
+int disco_profile_enable(disco_ctx* ctx, int on);
+int disco_profile_reset(disco_ctx* ctx);
+int disco_profile_get(disco_ctx* ctx, int kernel, long long* launches, double* total_ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,10 @@
+"""libdisco for MI355X: the hot path of the subtraction method for
+disconnected diagrams (Wilson-clover D and D_Lambda inversions on
+distillation sources, perambulators, loops, correlators) as HIP kernels for
+gfx950 behind a C ABI (include/disco.h).  This package holds the HIP sources
+(csrc/), the in-tree build, and a thin ctypes binding."""
+from .binding import (  # noqa: F401
+    Context, Domains, DiscoError, SolverParams, SolverStats, lib, exported_symbols,
+    F64, F32, BF16, G_1, G_5, G_X, G_Y, G_Z, CGNR_F64, BICGSTAB_DC, K_STENCIL,
+    OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ESTATE,
+)

@@ -1,0 +1,273 @@
+"""Thin ctypes binding of libdisco (include/disco.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device
+buffers are torch tensors on the GPU (complex128 unless stated); the context
+issues its work on torch's current stream.  The binding raises when the
+library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdisco.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+F64, F32, BF16 = 0, 1, 2
+HOST, DEVICE = 0, 1
+G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
+CGNR_F64, BICGSTAB_DC = 0, 1
+K_STENCIL = 0
+
+
+class DiscoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libdisco error %d: %s" % (code, msg))
+        self.code = code
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_block", ctypes.c_int),
+                ("fallback", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolverStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("converged", ctypes.c_int), ("true_rel_residual", ctypes.c_double)]
+
+
+_lib = None
+
+P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+_SIGS = {
+    "disco_create": ([P, P, I, P], I),
+    "disco_destroy": ([P], I),
+    "disco_set_stream": ([P, P], I),
+    "disco_last_error": ([P], ctypes.c_char_p),
+    "disco_gauge_set": ([P, P, I], I),
+    "disco_clover_setup": ([P, D, D], I),
+    "disco_clover_get": ([P, P], I),
+    "disco_domains_create": ([P, P, I, P], I),
+    "disco_domains_destroy": ([P], I),
+    "disco_dirac_apply": ([P, I, I, I, P, P], I),
+    "disco_dirac_block_apply": ([P, P, I, I, I, P, P], I),
+    "disco_native_bytes": ([P, I, I], LL),
+    "disco_to_native": ([P, I, I, P, P], I),
+    "disco_from_native": ([P, I, I, P, P], I),
+    "disco_dirac_apply_native": ([P, P, I, I, I, P, P], I),
+    "disco_solve_multi_rhs": ([P, P, ctypes.POINTER(SolverParams), I, P, P, ctypes.POINTER(SolverStats)], I),
+    "disco_profile_enable": ([P, I], I),
+    "disco_profile_reset": ([P], I),
+    "disco_profile_get": ([P, I, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)], I),
+}
+_OPTIONAL = {
+    "disco_ape_smear": ([P, I, D], I),
+    "disco_smeared_get": ([P, P], I),
+    "disco_laplace_eigvecs": ([P, I, D, P, P], I),
+    "disco_perambulator": ([P, P, I, I, I, P, P, I, P], I),
+    "disco_loops": ([P, P, I, I, P, P, I, P], I),
+    "disco_loops_distill": ([P, P, P, I, P, P, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
+    "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
+}
+
+
+def lib():
+    """Load libdisco.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdisco.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in list(_SIGS.items()) + list(_OPTIONAL.items()):
+            fn = getattr(h, name, None)
+            if fn is None:
+                if name in _SIGS:
+                    raise ImportError("libdisco.so lacks %s" % name)
+                continue
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS) + list(_OPTIONAL)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Domains:
+    def __init__(self, ctx: "Context", cut):
+        cut = np.ascontiguousarray(np.asarray(cut, dtype=np.uint8))
+        self.ctx = ctx
+        self.cut = cut
+        h = ctypes.c_void_p()
+        ctx._chk(lib().disco_domains_create(ctx.h, cut.ctypes.data_as(P), cut.shape[1], ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().disco_domains_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libdisco context for one lattice on one GPU."""
+
+    def __init__(self, dims, bc=(1, 1, 1, -1), device: int = 0):
+        torch = _torch()
+        self.dims = tuple(int(d) for d in dims)
+        self.bc = tuple(int(b) for b in bc)
+        self.V = int(np.prod(self.dims))
+        self.Vs = self.V // self.dims[3]
+        self.device = device
+        d = (ctypes.c_int * 4)(*self.dims)
+        b = (ctypes.c_int * 4)(*self.bc)
+        h = ctypes.c_void_p()
+        rc = lib().disco_create(d, b, device, ctypes.byref(h))
+        if rc != OK:
+            raise DiscoError(rc, "disco_create failed")
+        self.h = h
+        self.sync_stream()
+
+    # -- plumbing
+    def _chk(self, rc):
+        if rc != OK:
+            raise DiscoError(rc, lib().disco_last_error(self.h).decode())
+        return rc
+
+    def sync_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._chk(lib().disco_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().disco_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dev(self, a, dtype=None):
+        """numpy -> GPU torch tensor (complex128 by default)."""
+        torch = _torch()
+        t = torch.from_numpy(np.ascontiguousarray(a))
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.to("cuda:%d" % self.device)
+
+    def empty_spinors(self, n):
+        torch = _torch()
+        return torch.empty((n, self.V, 4, 3), dtype=torch.complex128, device="cuda:%d" % self.device)
+
+    # -- setup
+    def gauge_set(self, U):
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        self._chk(lib().disco_gauge_set(self.h, U.ctypes.data_as(P), HOST))
+
+    def gauge_set_device(self, U_t):
+        self._chk(lib().disco_gauge_set(self.h, _dptr(U_t), DEVICE))
+
+    def clover_setup(self, kappa, csw):
+        self._chk(lib().disco_clover_setup(self.h, float(kappa), float(csw)))
+
+    def clover_get(self):
+        torch = _torch()
+        A = torch.empty((self.V, 12, 12), dtype=torch.complex128, device="cuda:%d" % self.device)
+        self._chk(lib().disco_clover_get(self.h, _dptr(A)))
+        return A
+
+    def domains(self, cut) -> Domains:
+        return Domains(self, cut)
+
+    # -- operators
+    def dirac_apply(self, psi, prec=F64, dagger=False, out=None):
+        n = psi.shape[0]
+        out = self.empty_spinors(n) if out is None else out
+        self._chk(lib().disco_dirac_apply(self.h, prec, int(dagger), n, _dptr(psi), _dptr(out)))
+        return out
+
+    def dirac_block_apply(self, dom: Domains, psi, prec=F64, dagger=False, out=None):
+        n = psi.shape[0]
+        out = self.empty_spinors(n) if out is None else out
+        self._chk(lib().disco_dirac_block_apply(self.h, dom.h, prec, int(dagger), n, _dptr(psi), _dptr(out)))
+        return out
+
+    def native_bytes(self, prec, n):
+        return int(lib().disco_native_bytes(self.h, prec, n))
+
+    def to_native(self, prec, psi):
+        torch = _torch()
+        n = psi.shape[0]
+        out = torch.empty(self.native_bytes(prec, n), dtype=torch.uint8, device=psi.device)
+        self._chk(lib().disco_to_native(self.h, prec, n, _dptr(psi), _dptr(out)))
+        return out
+
+    def from_native(self, prec, nat, n):
+        out = self.empty_spinors(n)
+        self._chk(lib().disco_from_native(self.h, prec, n, _dptr(nat), _dptr(out)))
+        return out
+
+    def dirac_apply_native(self, dom, prec, nat_in, nat_out, n, dagger=False):
+        self._chk(lib().disco_dirac_apply_native(self.h, None if dom is None else dom.h, prec, int(dagger), n,
+                                                 _dptr(nat_in), _dptr(nat_out)))
+
+    # -- solver
+    @staticmethod
+    def params(method=BICGSTAB_DC, tol=1e-10, max_iter=0, inner_prec=F32, inner_tol=0.0, rhs_block=0,
+               fallback=1, check_every=0) -> SolverParams:
+        return SolverParams(method, tol, max_iter, inner_prec, inner_tol, rhs_block, fallback, check_every)
+
+    def solve_multi_rhs(self, b, params: SolverParams, dom: Domains | None = None, x=None, allow_noconv=False):
+        n = b.shape[0]
+        x = self.empty_spinors(n) if x is None else x
+        stats = (SolverStats * max(1, n))()
+        rc = lib().disco_solve_multi_rhs(self.h, None if dom is None else dom.h, ctypes.byref(params), n,
+                                         _dptr(b), _dptr(x), stats)
+        if rc == ENOCONV and allow_noconv:
+            pass
+        else:
+            self._chk(rc)
+        return x, [stats[i] for i in range(n)]
+
+    # -- profiling
+    def profile_enable(self, on=True):
+        self._chk(lib().disco_profile_enable(self.h, int(on)))
+
+    def profile_reset(self):
+        self._chk(lib().disco_profile_reset(self.h))
+
+    def profile_get(self, kernel=K_STENCIL):
+        n = LL()
+        ms = D()
+        by = D()
+        self._chk(lib().disco_profile_get(self.h, kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value

@@ -1,0 +1,733 @@
+// Krylov solvers for D x = b and D_Lambda x = b on batches of right-hand sides.
+//
+//   CGNR (all FP64): conjugate gradients on D^+ D x = D^+ b.  The plain
+//     reference solver; its residual r = b - D x is the true residual.
+//   BiCGStab-DC: BiCGStab in FP32 or BF16 storage (FP32 arithmetic) on the
+//     normalised defect, inside an FP64 defect-correction loop that keeps x,
+//     recomputes r = b - D x with the FP64 operator, and decides convergence
+//     on that true residual.  Optional FP64 CGNR fallback.
+//
+// Every Krylov scalar lives on the device: reductions produce deterministic
+// per-block partial sums that one small kernel per right-hand side folds in a
+// fixed order and turns into the next step's scalars, so an iteration never
+// waits for the host.  The host reads the per-RHS state every few iterations
+// to stop; right-hand sides that have converged are frozen by zero scalars.
+//
+// Vectors are native blocks ([plane][V][n], right-hand side fastest): the
+// flat unit index i of a block belongs to right-hand side i % n.  Vector
+// kernels use blocks whose size is a multiple of n, so every lane keeps one
+// right-hand side across its grid-stride loop.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "spinor_io.h"
+
+namespace {
+
+// Per right-hand-side solver state.  rr/bb belong to the outer (FP64, true
+// residual) level; irr/ibb to the inner Krylov iteration.
+struct RhsScal {
+    cd rho, alpha, omega, beta;
+    double rr, bb, irr, ibb, gam, scale;
+    int active, breakdown, outer_done, pad;
+};
+
+// --------------------------------------------------------------- vector units
+// One "unit" is the widest natural load of a storage format: 1 complex
+// (FP64 double2), 2 complex (FP32 float4) or 4 complex (BF16 uint4).
+template <class IO>
+struct Unit;
+template <>
+struct Unit<IO64> {
+    static constexpr int C = 1;
+    __device__ __forceinline__ static void ld(const void* p, long i, cx<double> c[1]) {
+        double2 v = ((const double2*)p)[i];
+        c[0] = mk(v.x, v.y);
+    }
+    __device__ __forceinline__ static void st(void* p, long i, const cx<double> c[1]) {
+        ((double2*)p)[i] = make_double2(c[0].re, c[0].im);
+    }
+};
+template <>
+struct Unit<IO32> {
+    static constexpr int C = 2;
+    __device__ __forceinline__ static void ld(const void* p, long i, cx<float> c[2]) {
+        float4 v = ((const float4*)p)[i];
+        c[0] = mk(v.x, v.y);
+        c[1] = mk(v.z, v.w);
+    }
+    __device__ __forceinline__ static void st(void* p, long i, const cx<float> c[2]) {
+        ((float4*)p)[i] = make_float4(c[0].re, c[0].im, c[1].re, c[1].im);
+    }
+};
+template <>
+struct Unit<IOBF> {
+    static constexpr int C = 4;
+    __device__ __forceinline__ static void ld(const void* p, long i, cx<float> c[4]) {
+        uint4 v = ((const uint4*)p)[i];
+        c[0] = mk(bf2f(v.x & 0xffffu), bf2f(v.x >> 16));
+        c[1] = mk(bf2f(v.y & 0xffffu), bf2f(v.y >> 16));
+        c[2] = mk(bf2f(v.z & 0xffffu), bf2f(v.z >> 16));
+        c[3] = mk(bf2f(v.w & 0xffffu), bf2f(v.w >> 16));
+    }
+    __device__ __forceinline__ static void st(void* p, long i, const cx<float> c[4]) {
+        ((uint4*)p)[i] = make_uint4(IOBF::pack(c[0]), IOBF::pack(c[1]), IOBF::pack(c[2]), IOBF::pack(c[3]));
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cast(cd a) {
+    return mk((T)a.re, (T)a.im);
+}
+
+struct VecGeo {
+    long total;  // units in the whole block (all right-hand sides)
+    int n;       // right-hand sides
+    int bd;      // threads per block (multiple of n)
+    int nb;      // blocks (= partial-sum slots per rhs and quantity)
+};
+
+#define VEC_LOOP(g) for (long i = (long)blockIdx.x * (g).bd + threadIdx.x; i < (g).total; i += (long)(g).nb * (g).bd)
+
+// partial ||v||^2 per right-hand side
+template <class IO>
+__global__ void k_norm2(const void* v, VecGeo g, double2* part) {
+    typedef Unit<IO> U;
+    typedef typename IO::T T;
+    double acc[2] = {0, 0};
+    VEC_LOOP(g) {
+        cx<T> a[U::C];
+        U::ld(v, i, a);
+#pragma unroll
+        for (int c = 0; c < U::C; c++) acc[0] += (double)nrm(a[c]);
+    }
+    rhs_partials<1>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
+}
+
+// dst (IOD) = scale[r] * src (IOS), site by site through the layout accessors
+// (the native layouts of different precisions order components differently)
+template <class IOS, class IOD>
+__global__ void k_copy_scale(const void* src, void* dst, long V, int n, const RhsScal* sc, int use_scale) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long s = j / n, r = j - s * n;
+        const double f = use_scale ? sc[r].scale : 1.0;
+        cx<typename IOS::T> a[12];
+        cx<typename IOD::T> b[12];
+        IOS::load(src, V, n, r, s, a);
+#pragma unroll
+        for (int k = 0; k < 12; k++)
+            b[k] = mk((typename IOD::T)(f * (double)a[k].re), (typename IOD::T)(f * (double)a[k].im));
+        IOD::store(dst, V, n, r, s, b);
+    }
+}
+
+// x64 += (1/scale[r]) * e (inner precision) for right-hand sides that ran
+template <class IO>
+__global__ void k_dc_update(double2* x64, const void* e, long V, int n, const RhsScal* sc) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long s = j / n, r = j - s * n;
+        if (sc[r].outer_done) continue;
+        const double f = sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0;
+        cx<typename IO::T> a[12];
+        cx<double> x[12];
+        IO::load(e, V, n, r, s, a);
+        IO64::load(x64, V, n, r, s, x);
+#pragma unroll
+        for (int k = 0; k < 12; k++) x[k] = mk(x[k].re + f * (double)a[k].re, x[k].im + f * (double)a[k].im);
+        IO64::store(x64, V, n, r, s, x);
+    }
+}
+
+template <class IO>
+__global__ void k_zero(void* v, long nunits_total) {
+    typedef typename IO::T T;
+    cx<T> z[Unit<IO>::C];
+#pragma unroll
+    for (int c = 0; c < Unit<IO>::C; c++) z[c] = mk((T)0, (T)0);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nunits_total; i += (long)gridDim.x * blockDim.x)
+        Unit<IO>::st(v, i, z);
+}
+
+// ---- BiCGStab vector steps
+// s = r - alpha v
+template <class IO>
+__global__ void k_bicg_s(const void* r_, const void* v_, void* s_, VecGeo g, const RhsScal* sc) {
+    typedef Unit<IO> U;
+    typedef typename IO::T T;
+    const cx<T> al = cast<T>(sc[threadIdx.x % g.n].alpha);
+    VEC_LOOP(g) {
+        cx<T> a[U::C], b[U::C], o[U::C];
+        U::ld(r_, i, a);
+        U::ld(v_, i, b);
+#pragma unroll
+        for (int c = 0; c < U::C; c++) o[c] = a[c] - al * b[c];
+        U::st(s_, i, o);
+    }
+}
+
+// x += alpha p + omega s ; r = s - omega t ; partials <rhat, r>, ||r||^2
+template <class IO>
+__global__ void k_bicg_xr(void* x_, const void* p_, const void* s_, const void* t_, void* r_, const void* rh_, VecGeo g,
+                          const RhsScal* sc, double2* part) {
+    typedef Unit<IO> U;
+    typedef typename IO::T T;
+    const int rr = threadIdx.x % g.n;
+    const cx<T> al = cast<T>(sc[rr].alpha), om = cast<T>(sc[rr].omega);
+    double acc[4] = {0, 0, 0, 0};
+    VEC_LOOP(g) {
+        cx<T> x[U::C], p[U::C], s[U::C], t[U::C], rh[U::C], rn[U::C];
+        U::ld(x_, i, x);
+        U::ld(p_, i, p);
+        U::ld(s_, i, s);
+        U::ld(t_, i, t);
+        U::ld(rh_, i, rh);
+#pragma unroll
+        for (int c = 0; c < U::C; c++) {
+            x[c] = x[c] + al * p[c] + om * s[c];
+            rn[c] = s[c] - om * t[c];
+        }
+        U::st(x_, i, x);
+        U::st(r_, i, rn);
+        U::ld(r_, i, rn);  // reductions on the stored (rounded) residual
+#pragma unroll
+        for (int c = 0; c < U::C; c++) {
+            cx<T> d = cjmul(rh[c], rn[c]);
+            acc[0] += (double)d.re;
+            acc[1] += (double)d.im;
+            acc[2] += (double)nrm(rn[c]);
+        }
+    }
+    rhs_partials<2>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
+}
+
+// p = r + beta (p - omega v)
+template <class IO>
+__global__ void k_bicg_p(void* p_, const void* r_, const void* v_, VecGeo g, const RhsScal* sc) {
+    typedef Unit<IO> U;
+    typedef typename IO::T T;
+    const int rr = threadIdx.x % g.n;
+    const cx<T> be = cast<T>(sc[rr].beta), om = cast<T>(sc[rr].omega);
+    VEC_LOOP(g) {
+        cx<T> p[U::C], r[U::C], v[U::C];
+        U::ld(p_, i, p);
+        U::ld(r_, i, r);
+        U::ld(v_, i, v);
+#pragma unroll
+        for (int c = 0; c < U::C; c++) p[c] = r[c] + be * (p[c] - om * v[c]);
+        U::st(p_, i, p);
+    }
+}
+
+// ---- CGNR vector steps (FP64)
+// x += alpha p ; r -= alpha w ; partial ||r||^2
+__global__ void k_cgnr_xr(double2* x, const double2* p, const double2* w, double2* rv, VecGeo g, const RhsScal* sc,
+                          double2* part) {
+    const double al = sc[threadIdx.x % g.n].alpha.re;
+    double acc[2] = {0, 0};
+    VEC_LOOP(g) {
+        double2 xv = x[i], pv = p[i], wv = w[i], r = rv[i];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        r.x -= al * wv.x;
+        r.y -= al * wv.y;
+        x[i] = xv;
+        rv[i] = r;
+        acc[0] += r.x * r.x + r.y * r.y;
+    }
+    rhs_partials<1>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
+}
+
+// p = z + beta p
+__global__ void k_cgnr_p(double2* p, const double2* z, VecGeo g, const RhsScal* sc) {
+    const double be = sc[threadIdx.x % g.n].beta.re;
+    VEC_LOOP(g) {
+        double2 pv = p[i], zv = z[i];
+        p[i] = make_double2(zv.x + be * pv.x, zv.y + be * pv.y);
+    }
+}
+
+// --------------------------------------------------------------- scalar steps
+// Each block folds the partial sums of one right-hand side in a fixed order.
+template <int NQ>
+__device__ __forceinline__ void fold(const double2* part, long r, int nparts, cd out[NQ]) {
+    double acc[2 * NQ];
+#pragma unroll
+    for (int k = 0; k < 2 * NQ; k++) acc[k] = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            double2 v = part[(r * NQ + q) * nparts + i];
+            acc[2 * q] += v.x;
+            acc[2 * q + 1] += v.y;
+        }
+    }
+    block_sum(acc);
+#pragma unroll
+    for (int q = 0; q < NQ; q++) out[q] = mk(acc[2 * q], acc[2 * q + 1]);
+}
+
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    double d = b.re * b.re + b.im * b.im;
+    return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+// mode 0: bb = rr = ||b||^2 (outer start); mode 1: rr = ||r||^2.  Then decide
+// outer convergence and set scale = 1/||r|| for the next defect.
+__global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mode, double tol2) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    if (mode == 0) {
+        s.bb = q[0].re;
+        s.rr = q[0].re;
+        s.outer_done = 0;
+    } else {
+        s.rr = q[0].re;
+    }
+    if (s.rr <= tol2 * s.bb) s.outer_done = 1;
+    s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
+}
+
+// inner BiCGStab start: rho = <rhat, r> = ||r||^2 (rhat = r)
+__global__ void k_sc_bicg_init(const double2* part, int nparts, RhsScal* sc) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    s.rho = q[0];
+    s.irr = q[0].re;
+    s.ibb = q[0].re;
+    s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
+    s.breakdown = 0;
+    s.alpha = s.omega = s.beta = mk(0.0, 0.0);
+}
+
+// partial <rhat, v> -> alpha = rho / <rhat, v>
+__global__ void k_sc_bicg_alpha(const double2* part, int nparts, RhsScal* sc) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    double den = q[0].re * q[0].re + q[0].im * q[0].im;
+    if (s.active && !(den > 1e-300)) {
+        s.active = 0;
+        s.breakdown = 1;
+    }
+    s.alpha = s.active ? cdiv(s.rho, q[0]) : mk(0.0, 0.0);
+}
+
+// partials ||t||^2, <t, s> -> omega
+__global__ void k_sc_bicg_omega(const double2* part, int nparts, RhsScal* sc) {
+    cd q[2];
+    fold<2>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    if (s.active && !(q[0].re > 0)) {
+        s.active = 0;
+        s.breakdown = 1;
+    }
+    s.omega = s.active ? mk(q[1].re / q[0].re, q[1].im / q[0].re) : mk(0.0, 0.0);
+    if (s.active && nrm(s.omega) == 0.0) {
+        s.active = 0;
+        s.breakdown = 1;
+        s.omega = mk(0.0, 0.0);
+    }
+}
+
+// partials <rhat, r>, ||r||^2 -> beta; convergence relative to the inner start
+__global__ void k_sc_bicg_beta(const double2* part, int nparts, RhsScal* sc, double tol2) {
+    cd q[2];
+    fold<2>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    if (!s.active) {
+        s.beta = mk(0.0, 0.0);
+        return;
+    }
+    s.irr = q[1].re;
+    cd rho_new = q[0];
+    if (nrm(s.rho) == 0.0) {
+        s.active = 0;
+        s.breakdown = 1;
+        s.beta = mk(0.0, 0.0);
+        return;
+    }
+    s.beta = cdiv(rho_new, s.rho) * cdiv(s.alpha, s.omega);
+    s.rho = rho_new;
+    if (s.irr <= tol2 * s.ibb) s.active = 0;
+    if (!s.active) s.beta = mk(0.0, 0.0);
+}
+
+// CGNR: mode 0 init gam = ||z||^2 ; mode 1 alpha = gam / ||w||^2 ; mode 2 rr = ||r||^2 ;
+//       mode 3 beta = ||z||^2 / gam
+__global__ void k_sc_cgnr(const double2* part, int nparts, RhsScal* sc, int mode, double tol2) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    double v = q[0].re;
+    if (mode == 0) {
+        s.gam = v;
+        s.active = (!s.outer_done && v > 0) ? 1 : 0;
+        s.breakdown = 0;
+    } else if (mode == 1) {
+        if (s.active && !(v > 0)) {
+            s.active = 0;
+            s.breakdown = 1;
+        }
+        s.alpha = mk(s.active ? s.gam / v : 0.0, 0.0);
+    } else if (mode == 2) {
+        s.rr = v;
+        if (s.rr <= tol2 * s.bb) s.active = 0;
+    } else {
+        s.beta = mk(s.active ? v / s.gam : 0.0, 0.0);
+        s.gam = v;
+    }
+}
+
+// --------------------------------------------------------------- host side
+struct Work {
+    disco_ctx* ctx;
+    int n;            // rhs in this block
+    long V;
+    RhsScal* sc;      // device [n]
+    double2* part;    // device partials
+    int nsb;          // stencil partial slots
+    std::vector<RhsScal> h;
+};
+
+static VecGeo vgeo(long V, int prec, int n) {
+    int C = prec == DISCO_F64 ? 1 : prec == DISCO_F32 ? 2 : 4;
+    VecGeo g;
+    g.n = n;
+    g.total = 12 * V / C * n;
+    g.bd = (kMaxBlock / n) * n;
+    long want = (g.total + g.bd - 1) / g.bd;
+    g.nb = (int)std::max(1L, std::min(want, 2048L));
+    return g;
+}
+
+static int site_grid(long V, int n) { return (int)std::min<long>((V * n + 255) / 256, 4096); }
+
+template <class IO>
+static void norm2(Work& w, const void* v, VecGeo g) {
+    hipLaunchKernelGGL(k_norm2<IO>, dim3(g.nb), dim3(g.bd), 0, w.ctx->stream, v, g, w.part);
+}
+
+template <class IOS, class IOD>
+static void copy_scale(Work& w, const void* src, void* dst, int use_scale) {
+    hipLaunchKernelGGL((k_copy_scale<IOS, IOD>), dim3(site_grid(w.V, w.n)), dim3(256), 0, w.ctx->stream, src, dst,
+                       w.V, w.n, w.sc, use_scale);
+}
+
+template <class IO>
+static void dc_update(Work& w, double2* x64, const void* e) {
+    hipLaunchKernelGGL((k_dc_update<IO>), dim3(site_grid(w.V, w.n)), dim3(256), 0, w.ctx->stream, x64, e, w.V, w.n,
+                       w.sc);
+}
+
+static void pull(Work& w) {
+    w.h.resize(w.n);
+    HIPCHK(hipMemcpyAsync(w.h.data(), w.sc, sizeof(RhsScal) * w.n, hipMemcpyDeviceToHost, w.ctx->stream));
+    HIPCHK(hipStreamSynchronize(w.ctx->stream));
+}
+
+static void push(Work& w, const std::vector<RhsScal>& h) {
+    HIPCHK(hipMemcpyAsync(w.sc, h.data(), sizeof(RhsScal) * w.n, hipMemcpyHostToDevice, w.ctx->stream));
+    HIPCHK(hipStreamSynchronize(w.ctx->stream));
+}
+
+static void stencil(Work& w, int prec, int dag, const void* in, void* out, const void* aux, const void* aux2,
+                    const uint8_t* mask, int epi) {
+    disco::StencilCall c{prec, dag, w.n, in, out, aux, aux2, mask, w.part, epi};
+    disco::stencil_launch(w.ctx, c);
+}
+
+// r64 = b64 - D x64 with the FP64 operator and ||r||^2 -> outer scalars (mode 1)
+static void outer_residual(Work& w, const double2* b64, const double2* x64, double2* r64, const uint8_t* mask,
+                           double tol2) {
+    stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
+    k_sc_outer<<<w.n, 256, 0, w.ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
+}
+
+// FP64 CGNR on D e = rhs (e starts at 0) to relative residual tol.  Uses and
+// overwrites the device state (bb/rr/outer_done of the rhs system).
+static void cgnr_run(Work& w, const double2* rhs, double2* e, const uint8_t* mask, double tol, int max_iter,
+                     int check_every, int* iters) {
+    disco_ctx* ctx = w.ctx;
+    VecGeo g = vgeo(w.V, DISCO_F64, w.n);
+    size_t nb = disco::native_bytes(ctx, DISCO_F64, w.n);
+    double2* r = (double2*)ws_get(ctx, "cg_r", nb);
+    double2* z = (double2*)ws_get(ctx, "cg_z", nb);
+    double2* p = (double2*)ws_get(ctx, "cg_p", nb);
+    double2* q = (double2*)ws_get(ctx, "cg_w", nb);
+    const double tol2 = tol * tol;
+    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(e, g.total);
+    copy_scale<IO64, IO64>(w, rhs, r, 0);
+    norm2<IO64>(w, r, g);
+    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, 0, tol2);
+    stencil(w, DISCO_F64, 1, r, z, nullptr, nullptr, mask, disco::EPI_NORM);
+    k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 0, tol2);
+    copy_scale<IO64, IO64>(w, z, p, 0);
+    int it = 0;
+    while (it < max_iter) {
+        for (int k = 0; k < check_every && it < max_iter; k++, it++) {
+            stencil(w, DISCO_F64, 0, p, q, nullptr, nullptr, mask, disco::EPI_NORM);
+            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
+            hipLaunchKernelGGL(k_cgnr_xr, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, q, r, g, w.sc, w.part);
+            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, 2, tol2);
+            stencil(w, DISCO_F64, 1, r, z, nullptr, nullptr, mask, disco::EPI_NORM);
+            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 3, tol2);
+            hipLaunchKernelGGL(k_cgnr_p, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, z, g, w.sc);
+        }
+        HIPCHK(hipGetLastError());
+        pull(w);
+        bool any = false;
+        for (auto& s : w.h) any |= s.active != 0;
+        if (!any) break;
+    }
+    *iters += it;
+}
+
+// inner BiCGStab on D e = rin (normalised defect) in storage IO
+template <class IO>
+static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol, int max_iter,
+                    int check_every) {
+    disco_ctx* ctx = w.ctx;
+    VecGeo g = vgeo(w.V, prec, w.n);
+    size_t nb = disco::native_bytes(ctx, prec, w.n);
+    void* r = ws_get(ctx, "bi_r", nb);
+    void* rh = ws_get(ctx, "bi_rh", nb);
+    void* p = ws_get(ctx, "bi_p", nb);
+    void* v = ws_get(ctx, "bi_v", nb);
+    void* s = ws_get(ctx, "bi_s", nb);
+    void* t = ws_get(ctx, "bi_t", nb);
+    k_zero<IO><<<1024, 256, 0, ctx->stream>>>(e, g.total);
+    copy_scale<IO, IO>(w, rin, r, 0);
+    copy_scale<IO, IO>(w, rin, rh, 0);
+    copy_scale<IO, IO>(w, rin, p, 0);
+    norm2<IO>(w, r, g);
+    k_sc_bicg_init<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc);
+    const double tol2 = inner_tol * inner_tol;
+    int it = 0;
+    while (it < max_iter) {
+        for (int k = 0; k < check_every && it < max_iter; k++, it++) {
+            stencil(w, prec, 0, p, v, nullptr, rh, mask, disco::EPI_DOTAUX);
+            k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+            hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
+            stencil(w, prec, 0, s, t, nullptr, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN);
+            k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+            hipLaunchKernelGGL(k_bicg_xr<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, r, rh, g, w.sc,
+                               w.part);
+            k_sc_bicg_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
+            hipLaunchKernelGGL(k_bicg_p<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, r, v, g, w.sc);
+        }
+        HIPCHK(hipGetLastError());
+        pull(w);
+        bool any = false;
+        for (auto& sc : w.h) any |= sc.active != 0;
+        if (!any) break;
+    }
+    return it;
+}
+
+static void fill_stats(Work& w, const disco_solver_params& P, int iters, int outer, int fb, disco_solver_stats* st) {
+    for (int i = 0; i < w.n; i++) {
+        st[i].iters = iters;
+        st[i].outer_iters = outer;
+        st[i].fallback_used = fb;
+        st[i].true_rel_residual = w.h[i].bb > 0 ? std::sqrt(w.h[i].rr / w.h[i].bb) : 0.0;
+        st[i].converged = st[i].true_rel_residual <= P.tol;
+    }
+}
+
+// FP64 CGNR correction of x64 on the current defect r64 (the fallback, and the
+// restart loop of the plain solver).  Restores the outer state afterwards and
+// recomputes the true residual.
+static void cgnr_correct(Work& w, const double2* b64, double2* x64, double2* r64, const uint8_t* mask, double tol,
+                         int max_iter, int check, int* iters) {
+    disco_ctx* ctx = w.ctx;
+    double2* e = (double2*)ws_get(ctx, "dc_ecg", disco::native_bytes(ctx, DISCO_F64, w.n));
+    pull(w);
+    const std::vector<RhsScal> outer_state = w.h;
+    double worst = 1e-300;
+    for (auto& s : outer_state)
+        if (!s.outer_done && s.bb > 0) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+    // relative target on the defect system: tol * ||b|| / ||r|| (with margin)
+    const double rtol = std::max(1e-16, 0.5 * tol / worst);
+    cgnr_run(w, r64, e, mask, rtol, max_iter, check, iters);
+    std::vector<RhsScal> h = outer_state;
+    for (auto& s : h) s.scale = 1.0;  // x += e for the right-hand sides still running
+    push(w, h);
+    dc_update<IO64>(w, x64, e);
+    push(w, outer_state);
+    outer_residual(w, b64, x64, r64, mask, tol * tol);
+    pull(w);
+}
+
+template <class IO>
+static void dc_solve(Work& w, const disco_solver_params& P, int prec, const double2* b64, double2* x64,
+                     const uint8_t* mask, disco_solver_stats* st) {
+    disco_ctx* ctx = w.ctx;
+    size_t nb64 = disco::native_bytes(ctx, DISCO_F64, w.n);
+    size_t nbp = disco::native_bytes(ctx, prec, w.n);
+    double2* r64 = (double2*)ws_get(ctx, "dc_r64", nb64);
+    void* rin = ws_get(ctx, "dc_rin", nbp);
+    void* e = ws_get(ctx, "dc_e", nbp);
+    VecGeo g64 = vgeo(w.V, DISCO_F64, w.n);
+    const double tol2 = P.tol * P.tol;
+    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+    norm2<IO64>(w, b64, g64);
+    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    copy_scale<IO64, IO64>(w, b64, r64, 0);
+    int iters = 0, outer = 0;
+    const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+    const int check = P.check_every > 0 ? P.check_every : 10;
+    const double itol = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-5);
+    const int inner_cap = 2000;
+    const bool trace = getenv("DISCO_TRACE") != nullptr;
+    double last_worst = 1e300;
+    int stall = 0;
+    while (true) {
+        pull(w);
+        bool done = true;
+        double worst = 0;
+        int nd = 0;
+        for (auto& s : w.h) {
+            done &= s.outer_done != 0;
+            nd += s.outer_done;
+            if (s.bb > 0) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+        }
+        if (trace)
+            fprintf(stderr, "[disco] outer %d: worst true rel residual %.3e, %d/%d done, %d inner iterations\n",
+                    outer, worst, nd, w.n, iters);
+        if (done || iters >= max_iter) break;
+        stall = worst > 0.5 * last_worst ? stall + 1 : 0;
+        last_worst = worst;
+        if (stall >= 3) break;  // no progress: leave it to the fallback
+        outer++;
+        copy_scale<IO64, IO>(w, r64, rin, 1);
+        iters += bicg_run<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+        dc_update<IO>(w, x64, e);
+        outer_residual(w, b64, x64, r64, mask, tol2);
+    }
+    int fb = 0;
+    pull(w);
+    bool done = true;
+    for (auto& s : w.h) done &= s.outer_done != 0;
+    if (!done && P.fallback) {
+        fb = 1;
+        int before = iters;
+        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, max_iter - iters), check, &iters);
+        if (trace) fprintf(stderr, "[disco] fallback CGNR %d iterations\n", iters - before);
+    }
+    fill_stats(w, P, iters, outer, fb, st);
+}
+
+static void cgnr_solve(Work& w, const disco_solver_params& P, const double2* b64, double2* x64, const uint8_t* mask,
+                       disco_solver_stats* st) {
+    disco_ctx* ctx = w.ctx;
+    double2* r64 = (double2*)ws_get(ctx, "dc_r64", disco::native_bytes(ctx, DISCO_F64, w.n));
+    VecGeo g64 = vgeo(w.V, DISCO_F64, w.n);
+    const double tol2 = P.tol * P.tol;
+    const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+    const int check = P.check_every > 0 ? P.check_every : 10;
+    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+    norm2<IO64>(w, b64, g64);
+    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    copy_scale<IO64, IO64>(w, b64, r64, 0);
+    int iters = 0, outer = 0;
+    // restarted from the true residual until it meets tol (a restart costs one
+    // extra FP64 stencil and guards against drift of the recursive residual)
+    while (true) {
+        pull(w);
+        bool done = true;
+        for (auto& s : w.h) done &= s.outer_done != 0;
+        if (done || iters >= max_iter || outer >= 8) break;
+        outer++;
+        cgnr_correct(w, b64, x64, r64, mask, P.tol, max_iter - iters, check, &iters);
+    }
+    fill_stats(w, P, iters, outer, 0, st);
+}
+
+}  // namespace
+
+namespace disco {
+
+// Solve on native FP64 blocks b64 -> x64 (n right-hand sides).
+void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
+                  double2* x64, disco_solver_stats* st) {
+    Work w;
+    w.ctx = ctx;
+    w.n = n;
+    w.V = ctx->V;
+    w.nsb = stencil_nsb(ctx, n);
+    w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
+    VecGeo g = vgeo(ctx->V, DISCO_F64, n);
+    size_t slots = (size_t)std::max(w.nsb, g.nb);
+    w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 3 * n);
+    HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
+    const uint8_t* mask = dom ? dom->d_mask : nullptr;
+    if (P.method == DISCO_CGNR_F64) {
+        cgnr_solve(w, P, b64, x64, mask, st);
+    } else if (P.method == DISCO_BICGSTAB_DC) {
+        if (P.inner_prec == DISCO_F32)
+            dc_solve<IO32>(w, P, DISCO_F32, b64, x64, mask, st);
+        else if (P.inner_prec == DISCO_BF16)
+            dc_solve<IOBF>(w, P, DISCO_BF16, b64, x64, mask, st);
+        else if (P.inner_prec == DISCO_F64)
+            dc_solve<IO64>(w, P, DISCO_F64, b64, x64, mask, st);
+        else
+            disco_throw(DISCO_EINVAL, "bad inner precision %d", P.inner_prec);
+    } else {
+        disco_throw(DISCO_EINVAL, "unknown solver method %d", P.method);
+    }
+}
+
+int default_rhs_block(const disco_solver_params& P, int nrhs) {
+    int b = P.rhs_block > 0 ? P.rhs_block : 16;
+    return std::max(1, std::min({b, nrhs, 64}));
+}
+
+}  // namespace disco
+
+extern "C" int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params* p, int nrhs,
+                                     const void* b, void* x, disco_solver_stats* stats) {
+    if (!ctx) return DISCO_EINVAL;
+    bool all_ok = true;
+    int rc = guarded(ctx, [&] {
+        REQUIRE(p && (nrhs == 0 || (b && x)), DISCO_EINVAL, "NULL argument");
+        REQUIRE(nrhs >= 0, DISCO_EINVAL, "nrhs < 0");
+        REQUIRE(p->tol > 0, DISCO_EINVAL, "tol must be > 0");
+        REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "solve before clover_setup");
+        activate(ctx);
+        if (nrhs == 0) return;
+        const int blk = disco::default_rhs_block(*p, nrhs);
+        const size_t field = (size_t)ctx->V * 12 * sizeof(double2);
+        std::vector<disco_solver_stats> st(blk);
+        for (int r0 = 0; r0 < nrhs; r0 += blk) {
+            int n = std::min(blk, nrhs - r0);
+            size_t nb64 = disco::native_bytes(ctx, DISCO_F64, n);
+            double2* b64 = (double2*)ws_get(ctx, "solve_b64", nb64);
+            double2* x64 = (double2*)ws_get(ctx, "solve_x64", nb64);
+            disco::to_native(ctx, DISCO_F64, n, (const char*)b + r0 * field, b64);
+            disco::solve_native(ctx, dom, *p, n, b64, x64, st.data());
+            disco::from_native(ctx, DISCO_F64, n, x64, (char*)x + r0 * field);
+            for (int i = 0; i < n; i++) {
+                if (stats) stats[r0 + i] = st[i];
+                all_ok &= st[i].converged != 0;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+    if (rc == DISCO_OK && !all_ok) {
+        ctx->err = "solver did not reach the tolerance for every right-hand side";
+        return DISCO_ENOCONV;
+    }
+    return rc;
+}

@@ -1,0 +1,185 @@
+"""GPU parity: clover term, D and D_Lambda (all precisions, dagger, multi-RHS)
+against the FP64 CPU oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def disco():
+    import paper_2609_37049_amd as d
+    d.lib()
+    return d
+
+
+def _setup(disco, dims, eps, seed, kappa, csw):
+    U = synth.gauge_field(dims, eps, seed)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, csw)
+    A = oracle.clover(U, dims, kappa, csw)
+    return ctx, U, A
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# lattices spanning several 256-site tiles with a ragged tail, L=2 wraps, odd extents
+LATTICES = [((4, 4, 4, 4), 1), ((2, 2, 2, 4), 2), ((6, 4, 4, 6), 3), ((3, 5, 2, 7), 4)]
+
+
+@pytest.mark.parametrize("dims,seed", LATTICES)
+def test_clover_parity(disco, dims, seed):
+    _say("clover", dims)
+    ctx, U, A = _setup(disco, dims, 0.5, seed, 0.12, 1.3)
+    Ag = ctx.clover_get().cpu().numpy()
+    assert _rel(Ag, A) < 1e-14
+
+
+@pytest.mark.parametrize("dims,seed", LATTICES)
+@pytest.mark.parametrize("nrhs", [1, 3, 4])
+def test_dirac_f64_parity(disco, dims, seed, nrhs):
+    _say("dirac f64", dims, nrhs)
+    ctx, U, A = _setup(disco, dims, 0.5, seed, 0.12, 1.3)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, nrhs, seed + 100)
+    for dag in (False, True):
+        out = ctx.dirac_apply(ctx.dev(psi), disco.F64, dag).cpu().numpy()
+        ref = oracle.dirac(U, A, dims, BC, 0.12, psi, dagger=dag)
+        assert _rel(out, ref) < 1e-14, (dag, _rel(out, ref))
+
+
+@pytest.mark.parametrize("prec,tol", [("F32", 2e-6), ("BF16", 1.5e-2)])
+@pytest.mark.parametrize("nrhs", [1, 2, 8])
+def test_dirac_low_precision(disco, prec, tol, nrhs):
+    dims = (6, 4, 4, 6)
+    _say("dirac", prec, nrhs)
+    ctx, U, A = _setup(disco, dims, 0.5, 7, 0.125, 1.5)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, nrhs, 8)
+    p = getattr(disco, prec)
+    for dag in (False, True):
+        out = ctx.dirac_apply(ctx.dev(psi), p, dag).cpu().numpy()
+        ref = oracle.dirac(U, A, dims, BC, 0.125, psi, dagger=dag)
+        assert _rel(out, ref) < tol
+
+
+@pytest.mark.parametrize("block", [(2, 2, 2, 2), (3, 2, 4, 3), (6, 4, 4, 6), (1, 1, 1, 1), (6, 4, 4, 2)])
+def test_block_dirac_parity(disco, block):
+    dims = (6, 4, 4, 6)
+    _say("block dirac", block)
+    ctx, U, A = _setup(disco, dims, 0.5, 9, 0.12, 1.1)
+    V = int(np.prod(dims))
+    cut = synth.tiling_cuts(dims, block)
+    dom = ctx.domains(cut)
+    psi = synth.random_spinor(V, 2, 10)
+    for dag in (False, True):
+        out = ctx.dirac_block_apply(dom, ctx.dev(psi), disco.F64, dag).cpu().numpy()
+        ref = oracle.dirac(U, A, dims, BC, 0.12, psi, cut=cut, dagger=dag)
+        assert _rel(out, ref) < 1e-14
+    out = ctx.dirac_block_apply(dom, ctx.dev(psi), disco.F32).cpu().numpy()
+    assert _rel(out, oracle.dirac(U, A, dims, BC, 0.12, psi, cut=cut)) < 2e-6
+
+
+def test_offset_domains_parity(disco):
+    dims = (12, 12, 8, 12)
+    _say("offset domains")
+    ctx, U, A = _setup(disco, dims, 0.25, 11, 0.126, 1.6)
+    cut = synth.offset_tiling_cuts(dims, (6, 6, 8, 12))
+    dom = ctx.domains(cut)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, 4, 12)
+    out = ctx.dirac_block_apply(dom, ctx.dev(psi), disco.F64).cpu().numpy()
+    assert _rel(out, oracle.dirac(U, A, dims, BC, 0.126, psi, cut=cut)) < 1e-14
+
+
+def test_native_roundtrip_and_native_apply(disco):
+    dims = (4, 4, 4, 8)
+    ctx, U, A = _setup(disco, dims, 0.3, 13, 0.12, 1.0)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, 4, 14)
+    t = ctx.dev(psi)
+    for p in (disco.F64, disco.F32, disco.BF16):
+        back = ctx.from_native(p, ctx.to_native(p, t), 4).cpu().numpy()
+        tol = {disco.F64: 0, disco.F32: 6e-8, disco.BF16: 4e-3}[p]
+        assert np.abs(back - psi).max() <= tol * np.abs(psi).max()
+    nat = ctx.to_native(disco.F64, t)
+    out = ctx.to_native(disco.F64, t)
+    ctx.dirac_apply_native(None, disco.F64, nat, out, 4)
+    res = ctx.from_native(disco.F64, out, 4).cpu().numpy()
+    assert _rel(res, oracle.dirac(U, A, dims, BC, 0.12, psi)) < 1e-14
+
+
+def test_bf16_rounding_is_nearest_even(disco):
+    """BF16 storage rounds FP64 inputs to the nearest bf16 value, ties to even."""
+    dims = (2, 2, 2, 2)
+    ctx = disco.Context(dims, BC)
+    V = 16
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -8 + 2 ** -30, -1.0 - 2 ** -8,
+                     3.14159265358979, 1e-3, 65504.0, 2.0 ** -100, 1.0 + 2 ** -9, 0.0, -2.5], dtype=np.float64)
+    psi = np.zeros((1, V, 4, 3), dtype=np.complex128)
+    psi[0, 0].reshape(-1)[:] = vals + 1j * vals[::-1]
+    back = ctx.from_native(disco.BF16, ctx.to_native(disco.BF16, ctx.dev(psi)), 1).cpu().numpy()[0, 0].reshape(-1)
+
+    def rne(x):
+        # nearest bf16 (8 significant bits) with ties to even, from the definition
+        if x == 0:
+            return 0.0
+        e = np.floor(np.log2(abs(x)))
+        q = x / 2.0 ** (e - 7)
+        f = np.floor(q)
+        r = q - f
+        if r > 0.5 or (r == 0.5 and int(f) % 2 == 1):
+            f += 1
+        return f * 2.0 ** (e - 7)
+    for k, v in enumerate(vals):
+        assert back[k].real == rne(v), (v, back[k].real, rne(v))
+        assert back[k].imag == rne(vals[::-1][k])
+
+
+def test_gauge_set_rejects_non_su3(disco):
+    dims = (2, 2, 2, 2)
+    ctx = disco.Context(dims, BC)
+    U = synth.gauge_field(dims, 0.3, 1)
+    U[3, 1] *= 1.001
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.gauge_set(U)
+    assert e.value.code == disco.EINVAL
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.clover_setup(0.1, 1.0)
+    assert e.value.code == disco.ESTATE
+
+
+def test_full_size_precision_workload_operator(disco):
+    """16^3 x 32 (the mixed-precision workload): D and D_Lambda in FP64 and FP32
+    against the oracle, element by element, on a 16-RHS block."""
+    pre = synth.PRESETS["prec_16x16x16x32"]
+    dims = pre.dims
+    _say("full-size operator", dims)
+    ctx, U, A = _setup(disco, dims, pre.eps, pre.seed, pre.kappa, pre.csw)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, 16, 77)
+    cut = synth.tiling_cuts(dims, pre.block)
+    dom = ctx.domains(cut)
+    t = ctx.dev(psi)
+    sample = [0, 5, 15]
+    ref = oracle.dirac(U, A, dims, BC, pre.kappa, psi[sample])
+    refb = oracle.dirac(U, A, dims, BC, pre.kappa, psi[sample], cut=cut)
+    for p, tol in ((disco.F64, 1e-14), (disco.F32, 2e-6)):
+        out = ctx.dirac_apply(t, p).cpu().numpy()
+        assert _rel(out[sample], ref) < tol
+        outb = ctx.dirac_block_apply(dom, t, p).cpu().numpy()
+        assert _rel(outb[sample], refb) < tol

@@ -1,0 +1,132 @@
+"""GPU parity of the solvers: FP64 CGNR and BiCGStab with FP32/BF16 inner
+solves inside FP64 defect correction, full and domain-restricted operators.
+Judged by the oracle: its own solution on small lattices, and the true
+residual computed with the oracle's operator at the full workload size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def disco():
+    import paper_2609_37049_amd as d
+    d.lib()
+    return d
+
+
+@pytest.fixture(scope="module")
+def plain(disco):
+    pre = synth.PRESETS["plain_4x4x4x4"]
+    U = synth.gauge_field(pre.dims, pre.eps, pre.seed)
+    ctx = disco.Context(pre.dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(pre.kappa, pre.csw)
+    A = oracle.clover(U, pre.dims, pre.kappa, pre.csw)
+    return pre, ctx, U, A
+
+
+def _true_rel_res(U, A, dims, kappa, b, x, cut=None):
+    r = b - oracle.dirac(U, A, dims, BC, kappa, x, cut=cut)
+    return np.sqrt(np.sum(np.abs(r) ** 2, axis=(1, 2, 3)) / np.sum(np.abs(b) ** 2, axis=(1, 2, 3)))
+
+
+@pytest.mark.parametrize("method,inner", [("CGNR_F64", "F64"), ("BICGSTAB_DC", "F32"), ("BICGSTAB_DC", "BF16"),
+                                          ("BICGSTAB_DC", "F64")])
+@pytest.mark.parametrize("blocked", [False, True])
+def test_solver_matches_oracle_small(disco, plain, method, inner, blocked):
+    pre, ctx, U, A = plain
+    _say("solve", method, inner, blocked)
+    dims = pre.dims
+    V = int(np.prod(dims))
+    cut = synth.tiling_cuts(dims, pre.block) if blocked else None
+    dom = ctx.domains(cut) if blocked else None
+    b = synth.random_spinor(V, 5, 31)
+    tol = 1e-12
+    P = ctx.params(method=getattr(disco, method), tol=tol, inner_prec=getattr(disco, inner), rhs_block=4)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, dom)
+    x = x.cpu().numpy()
+    rr = _true_rel_res(U, A, dims, pre.kappa, b, x, cut)
+    assert rr.max() <= tol * 1.01, rr
+    assert all(s.converged for s in st)
+    # both are evaluations of the same residual; below ~1e-14 FP64 rounding of b - D x dominates
+    rep = [s.true_rel_residual for s in st]
+    assert all(abs(a - r) <= max(1e-2 * r, 2e-15) for a, r in zip(rep, rr)), (rep, list(rr))
+    xo, _, _ = oracle.cgnr(U, A, dims, BC, pre.kappa, b[2], cut=cut, tol=1e-13)
+    assert np.abs(x[2] - xo).max() / np.abs(xo).max() < 1e-10
+
+
+def test_solver_zero_rhs_and_empty(disco, plain):
+    pre, ctx, U, A = plain
+    V = int(np.prod(pre.dims))
+    b = np.zeros((2, V, 4, 3), dtype=np.complex128)
+    b[1] = synth.random_spinor(V, 1, 3)[0]
+    P = ctx.params(tol=1e-11)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P)
+    x = x.cpu().numpy()
+    assert np.abs(x[0]).max() == 0
+    assert st[1].true_rel_residual <= 1e-11
+    x, st = ctx.solve_multi_rhs(ctx.dev(b[:0]), P)
+    assert x.shape[0] == 0
+
+
+def test_solver_reports_noconv(disco, plain):
+    pre, ctx, U, A = plain
+    V = int(np.prod(pre.dims))
+    b = synth.random_spinor(V, 2, 5)
+    P = ctx.params(method=disco.CGNR_F64, tol=1e-12, max_iter=3)
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.solve_multi_rhs(ctx.dev(b), P)
+    assert e.value.code == disco.ENOCONV
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, allow_noconv=True)
+    assert not st[0].converged and st[0].true_rel_residual > 1e-12
+
+
+def test_batched_equals_unbatched(disco, plain):
+    pre, ctx, U, A = plain
+    V = int(np.prod(pre.dims))
+    b = synth.random_spinor(V, 8, 41)
+    out = {}
+    for blk in (1, 2, 8):
+        P = ctx.params(tol=1e-12, rhs_block=blk)
+        out[blk] = ctx.solve_multi_rhs(ctx.dev(b), P)[0].cpu().numpy()
+    for blk in (1, 2):
+        assert np.abs(out[blk] - out[8]).max() / np.abs(out[8]).max() < 1e-10
+
+
+def test_full_size_mixed_precision_solve(disco):
+    """16^3 x 32 mixed-precision workload: FP32 and BF16 inner BiCGStab with
+    FP64 defect correction to 1e-10, full and block operator; the true
+    residual is recomputed with the oracle's FP64 operator."""
+    pre = synth.PRESETS["prec_16x16x16x32"]
+    dims = pre.dims
+    _say("full-size solve", dims)
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(pre.kappa, pre.csw)
+    A = oracle.clover(U, dims, pre.kappa, pre.csw)
+    V = int(np.prod(dims))
+    cut = synth.tiling_cuts(dims, pre.block)
+    dom = ctx.domains(cut)
+    b = synth.random_spinor(V, 16, 55)
+    for inner in (disco.F32, disco.BF16):
+        for d, c in ((None, None), (dom, cut)):
+            _say("  inner", inner, "block" if d else "full")
+            P = ctx.params(tol=1e-10, inner_prec=inner, rhs_block=16)
+            x, st = ctx.solve_multi_rhs(ctx.dev(b), P, d)
+            x = x.cpu().numpy()
+            rr = _true_rel_res(U, A, dims, pre.kappa, b[:3], x[:3], c)
+            assert rr.max() <= 1e-10 * 1.01, rr
+            assert all(s.converged for s in st)
