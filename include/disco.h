@@ -130,11 +130,12 @@ int disco_dirac_apply(disco_ctx* ctx, int prec, int dagger, int nrhs, const void
 int disco_dirac_block_apply(disco_ctx* ctx, const disco_domains* dom, int prec, int dagger, int nrhs,
                             const void* in, void* out);
 
-/* Internal ("native") spinor layout, for callers that keep fields resident:
- *   F64  : [r][12][V] complex double, plane k = spin*3 + colour
- *   F32  : [r][6][V]  float4 = components (2p, 2p+1) as (re, im, re, im)
- *   BF16 : [r][3][V]  16 bytes = components 4q..4q+3 as bf16 (re, im) pairs
- * disco_native_bytes gives the size of an nrhs block. */
+/* Internal ("native") layout of an nrhs block, for callers that keep fields
+ * resident; element (plane, site s, rhs r) at (plane*V + s)*nrhs + r:
+ *   F64  : [12][V][nrhs] complex double, plane k = spin*3 + colour
+ *   F32  : [6][V][nrhs]  float4 = components (2p, 2p+1) as (re, im, re, im)
+ *   BF16 : [3][V][nrhs]  16 bytes = components 4q..4q+3 as bf16 (re, im) pairs
+ * disco_native_bytes gives the size of an nrhs block (nrhs <= 256 per call). */
 long long disco_native_bytes(const disco_ctx* ctx, int prec, int nrhs);
 int disco_to_native(disco_ctx* ctx, int prec, int nrhs, const void* in_canonical, void* out_native);
 int disco_from_native(disco_ctx* ctx, int prec, int nrhs, const void* in_native, void* out_canonical);
@@ -169,12 +170,85 @@ typedef struct {
 int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params* p,
                           int nrhs, const void* b, void* x, disco_solver_stats* stats);
 
+/* ---------------------------------------------------------------- distillation
+ * Sources are built from the lowest eigenvectors v_i(t) of the gauge-covariant
+ * 3-D Laplacian on APE-smeared links (standard distillation, the "Analysis with
+ * standard distillation" subsection; eigenpairs per timeslice as in the
+ * Gaussian-profiled subsection). */
+
+/* APE smearing of the spatial links: `steps` sweeps of
+ *   U_k <- P_SU(3)[(1 - alpha) U_k + (alpha/4) * (sum of the 4 spatial staples)]
+ * with all links of a sweep updated from the previous sweep, P_SU(3) the polar
+ * factor M (M^+ M)^{-1/2} divided by the principal cube root of its
+ * determinant.  The smeared links are kept in the context and used only by the
+ * Laplacian; D keeps the unsmeared links.  steps = 0 makes the Laplacian use
+ * the unsmeared links.  ESTATE before disco_gauge_set. */
+int disco_ape_smear(disco_ctx* ctx, int steps, double alpha);
+/* Smeared links as [V][4][3][3] complex128 (device; time links unsmeared). */
+int disco_smeared_get(disco_ctx* ctx, void* U_out);
+/* out = -Delta in for nvec colour fields [nvec][V][3] complex128 (device):
+ *   -Delta psi(x) = sum_{k=1..3} [2 psi(x) - U_k(x) psi(x+k) - U_k(x-k)^+ psi(x-k)],
+ * smeared links if disco_ape_smear ran, else the gauge links. */
+int disco_laplace_apply(disco_ctx* ctx, int nvec, const void* in, void* out);
+/* Lowest nv eigenpairs of -Delta on every timeslice, eigenvalues ascending.
+ * Vev (device, [T][nv][Vs][3] complex128) receives orthonormal eigenvectors
+ * (arbitrary phases), lambda (host, [T][nv]) the eigenvalues.  tol bounds the
+ * eigenvector residual ||-Delta v - lambda v|| (<= 0: 1e-12).  ENOCONV when
+ * the eigensolver stops above tol. */
+int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vev, double* lambda);
+/* Perambulator projection tau[k][j][beta][r] = sum_{xs,c} conj(v_j(t_k; xs)_c)
+ * X_r(t_k, xs)_{beta,c} for solutions X (device, [nsrc][V][4][3] complex128,
+ * nsrc <= 64) at the sink timeslices t_snk[0..n_snk-1] (host ints): the sink
+ * side of V^+ D^-1 V.  Vev as above (device); tau (device) [n_snk][nv][4][nsrc]. */
+int disco_perambulator(disco_ctx* ctx, const void* Vev, int nv, int nsrc, const void* X, const int* t_snk, int n_snk,
+                       void* tau);
+/* Quark loops from diagonal elementals (Gamma (x) diag(w), the elementals
+ * equation of the Gaussian-profiled subsection; w = 1 is standard
+ * distillation): L[g][t] = sum_i w[t][i] sum_{a,b} Gamma_ab tau[t][i][b][i][a]
+ * with tau_tt (device, [T][nv][4][nv][4]) = tau(t,t), w (device [T][nv], or
+ * NULL for 1), gammas (host, DISCO_G_* codes), L (device, [ngamma][T]).  This
+ * is the zero-momentum loop sum_x Tr[Gamma D^-1(x,x)] of the Methodology
+ * section in its distillation form (no 1/Vs, no sign). */
+int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double* w, const int* gammas, int ngamma,
+                void* L);
+/* End-to-end loops: for every timeslice t and every (i, alpha) solve
+ * D x = v_i(t) (x) e_alpha (dom = NULL) or D_Lambda x = ... (dom given),
+ * project at t, and form the loops as in disco_loops.  With domains, sources
+ * of timeslices in different temporal layers of the partition are added into
+ * one multi-site source and solved together (exact, because D_Lambda does not
+ * couple different layers: the multi-site sources of the Cost section).
+ * Vev device [T][nv][Vs][3]; w device or NULL; L device [ngamma][T]; tau_out
+ * device [T][nv][4][nv][4] or NULL; agg (host, may be NULL) gets the summed
+ * iterations and the worst true residual.  T <= 64.  ENOCONV if any solve
+ * misses p->tol. */
+int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vev, int nv, const double* w,
+                        const int* gammas, int ngamma, const disco_solver_params* p, void* L, void* tau_out,
+                        disco_solver_stats* agg);
+/* Right-hand sides solved by the last disco_loops_distill call (packed count). */
+long long disco_last_solves(const disco_ctx* ctx);
+/* Disconnected correlators (Methodology equations Cdisc, correlator_factorised,
+ * subtracted_correlator, and corr1-corr4 of the Gaussian-profiled subsection),
+ * averaged over source times y0 (Results):
+ *   C(dt) = (1/|Y|) sum_{y0 in Y} [ <La(y0+dt mod T) Lb(y0)> - VEV ],
+ *   VEV = <La(x0)><Lb(y0)> (vev_mode 0) or (mean over cfg and t of La) times
+ *   the same of Lb (vev_mode 1), <.> the mean over configurations.
+ * Inputs (device, [ncfg][T] complex128): loops L of Gamma and Lt of
+ * Gamma-tilde = gamma_4 Gamma^+ gamma_4 for the full operator and for the
+ * domain-restricted one.  Outputs (device, [T] complex128): C_full = C^(d),
+ * C_fact = C^(d)_{L0,L1} from the restricted loops, dC = C_full - C_fact;
+ * four_terms (device [4][T] or NULL): block-block, block-delta, delta-block,
+ * delta-delta with delta L = L - L_Lambda.  y0_set (host) NULL = all T. */
+int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, const void* L_blk, const void* Lt_blk,
+                     int ncfg, int T, const int* y0_set, int ny0, int vev_mode, void* C_full, void* C_fact, void* dC,
+                     void* four_terms);
+
 /* ---------------------------------------------------------------- profiling
  * Per-kernel-family timing of launches made while profiling is on, measured
  * with HIP events recorded on the context's stream around each launch.
- * kernel: 0 = Wilson-clover stencil (any precision).  bytes = algorithmic
+ * kernel: 0 = Wilson-clover stencil (any precision): bytes = algorithmic
  * bytes of those launches (each input/output spinor, the links and the clover
- * term counted once per site). */
+ * term counted once per site); 1 = FP64 matrix-core contraction (perambulator,
+ * eigensolver Gram matrices): bytes holds the flop count instead. */
 int disco_profile_enable(disco_ctx* ctx, int on);
 int disco_profile_reset(disco_ctx* ctx);
 int disco_profile_get(disco_ctx* ctx, int kernel, long long* launches, double* total_ms, double* bytes);

@@ -64,15 +64,18 @@ _SIGS = {
     "disco_profile_reset": ([P], I),
     "disco_profile_get": ([P, I, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)], I),
 }
-_OPTIONAL = {
+_SIGS.update({
     "disco_ape_smear": ([P, I, D], I),
     "disco_smeared_get": ([P, P], I),
+    "disco_laplace_apply": ([P, I, P, P], I),
     "disco_laplace_eigvecs": ([P, I, D, P, P], I),
-    "disco_perambulator": ([P, P, I, I, I, P, P, I, P], I),
+    "disco_perambulator": ([P, P, I, I, P, P, I, P], I),
     "disco_loops": ([P, P, I, I, P, P, I, P], I),
     "disco_loops_distill": ([P, P, P, I, P, P, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
+    "disco_last_solves": ([P], LL),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
-}
+})
+_OPTIONAL = {}
 
 
 def lib():
@@ -257,6 +260,73 @@ class Context:
         else:
             self._chk(rc)
         return x, [stats[i] for i in range(n)]
+
+    # -- distillation
+    def ape_smear(self, steps, alpha):
+        self._chk(lib().disco_ape_smear(self.h, int(steps), float(alpha)))
+
+    def smeared_get(self):
+        torch = _torch()
+        out = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device="cuda:%d" % self.device)
+        self._chk(lib().disco_smeared_get(self.h, _dptr(out)))
+        return out
+
+    def laplace_apply(self, y):
+        torch = _torch()
+        out = torch.empty_like(y)
+        self._chk(lib().disco_laplace_apply(self.h, y.shape[0], _dptr(y), _dptr(out)))
+        return out
+
+    def laplace_eigvecs(self, nv, tol=1e-12):
+        torch = _torch()
+        T = self.dims[3]
+        Vev = torch.empty((T, nv, self.Vs, 3), dtype=torch.complex128, device="cuda:%d" % self.device)
+        lam = np.empty((T, nv), dtype=np.float64)
+        self._chk(lib().disco_laplace_eigvecs(self.h, int(nv), float(tol), _dptr(Vev), lam.ctypes.data_as(P)))
+        return Vev, lam
+
+    def perambulator(self, Vev, X, t_snk):
+        torch = _torch()
+        nv = Vev.shape[1]
+        t = np.ascontiguousarray(np.asarray(t_snk, dtype=np.int32))
+        tau = torch.empty((len(t), nv, 4, X.shape[0]), dtype=torch.complex128, device=X.device)
+        self._chk(lib().disco_perambulator(self.h, _dptr(Vev), nv, X.shape[0], _dptr(X), t.ctypes.data_as(P),
+                                           len(t), _dptr(tau)))
+        return tau
+
+    def loops(self, tau_tt, gammas, w=None):
+        torch = _torch()
+        T, nv = tau_tt.shape[0], tau_tt.shape[1]
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+        L = torch.empty((len(g), T), dtype=torch.complex128, device=tau_tt.device)
+        self._chk(lib().disco_loops(self.h, _dptr(tau_tt), T, nv, _dptr(w), g.ctypes.data_as(P), len(g), _dptr(L)))
+        return L
+
+    def loops_distill(self, Vev, gammas, params: SolverParams, dom: Domains | None = None, w=None, want_tau=False):
+        torch = _torch()
+        T, nv = Vev.shape[0], Vev.shape[1]
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+        L = torch.empty((len(g), T), dtype=torch.complex128, device=Vev.device)
+        tau = torch.empty((T, nv, 4, nv, 4), dtype=torch.complex128, device=Vev.device) if want_tau else None
+        agg = SolverStats()
+        self._chk(lib().disco_loops_distill(self.h, None if dom is None else dom.h, _dptr(Vev), nv, _dptr(w),
+                                            g.ctypes.data_as(P), len(g), ctypes.byref(params), _dptr(L), _dptr(tau),
+                                            ctypes.byref(agg)))
+        return L, tau, agg
+
+    def last_solves(self):
+        return int(lib().disco_last_solves(self.h))
+
+    def correlator(self, L_full, Lt_full, L_blk, Lt_blk, y0s=None, vev_mode=1):
+        torch = _torch()
+        ncfg, T = L_full.shape
+        y = None if y0s is None else np.ascontiguousarray(np.asarray(y0s, dtype=np.int32))
+        mk = lambda *s: torch.empty(s, dtype=torch.complex128, device=L_full.device)
+        C, Cf, dC, four = mk(T), mk(T), mk(T), mk(4, T)
+        self._chk(lib().disco_correlator(self.h, _dptr(L_full), _dptr(Lt_full), _dptr(L_blk), _dptr(Lt_blk), ncfg, T,
+                                         None if y is None else y.ctypes.data_as(P), 0 if y is None else len(y),
+                                         int(vev_mode), _dptr(C), _dptr(Cf), _dptr(dC), _dptr(four)))
+        return C, Cf, dC, four
 
     # -- profiling
     def profile_enable(self, on=True):

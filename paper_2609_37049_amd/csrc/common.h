@@ -92,6 +92,9 @@ struct disco_ctx {
     // named, grow-only device workspaces
     std::map<std::string, std::pair<void*, size_t>> ws;
 
+    // right-hand sides solved by the last distillation driver call (packed count)
+    long long last_solves = 0;
+
     // profiling
     bool prof_on = false;
     std::vector<ProfRec> prof;

@@ -428,6 +428,8 @@ int disco_domains_destroy(disco_domains* d) {
     return DISCO_OK;
 }
 
+long long disco_last_solves(const disco_ctx* ctx) { return ctx ? ctx->last_solves : -1; }
+
 int disco_profile_enable(disco_ctx* ctx, int on) {
     if (!ctx) return DISCO_EINVAL;
     ctx->prof_on = on != 0;

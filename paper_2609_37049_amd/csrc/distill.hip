@@ -1,0 +1,951 @@
+// Distillation on the GPU: APE smearing of the spatial links, the gauge-
+// covariant 3-D Laplacian and its lowest eigenvectors per timeslice, the
+// distillation sources v_i(t) (x) e_alpha (several timeslices packed into one
+// source for the domain-restricted operator), the perambulator projection
+// V^+ X on FP64 matrix cores, loops Tr[Gamma tau(t,t)] and the disconnected
+// correlators (full, completely factorised, subtracted, four-term split).
+//
+// Eigenvector blocks use the layout [t][xs*3 + c][j] (vector index j fastest,
+// K = 3 Vs rows per timeslice), so that the Laplacian stencil reads coalesced
+// rows and the Gram / projection contractions are plain row-major matrices.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "dense_host.h"
+#include "spinor_io.h"
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+namespace disco {
+void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
+                  double2* x64, disco_solver_stats* st);
+int default_rhs_block(const disco_solver_params& P, int nrhs);
+}  // namespace disco
+
+namespace {
+
+// ------------------------------------------------------------------ SU(3) helpers (FP64)
+__device__ __forceinline__ void m3mul(const cd* a, const cd* b, cd* c, bool da = false, bool db = false) {
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cd s = mk(0.0, 0.0);
+            for (int k = 0; k < 3; k++) {
+                cd x = da ? cj(a[k * 3 + i]) : a[i * 3 + k];
+                cd y = db ? cj(b[j * 3 + k]) : b[k * 3 + j];
+                s = s + x * y;
+            }
+            c[i * 3 + j] = s;
+        }
+}
+
+__device__ __forceinline__ cd det3(const cd* m) {
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// W = M (M^+ M)^{-1/2} by the Newton iteration W <- (W + W^{-+})/2 (with
+// the usual determinant-based scaling), then W / det(W)^{1/3} (principal
+// cube root).  The polar factor is unique, so this matches any other
+// evaluation of it; it commutes with M -> A M B^+ for unitary A, B.
+__device__ void su3_project(const cd* M, cd* W) {
+    cd X[9];
+    for (int k = 0; k < 9; k++) X[k] = M[k];
+    for (int it = 0; it < 30; it++) {
+        // inverse-transpose-conjugate: X^{-+} = cof(X)^* / det(X)^*
+        cd d = det3(X);
+        cd cof[9];
+        cof[0] = X[4] * X[8] - X[5] * X[7];
+        cof[1] = X[5] * X[6] - X[3] * X[8];
+        cof[2] = X[3] * X[7] - X[4] * X[6];
+        cof[3] = X[2] * X[7] - X[1] * X[8];
+        cof[4] = X[0] * X[8] - X[2] * X[6];
+        cof[5] = X[1] * X[6] - X[0] * X[7];
+        cof[6] = X[1] * X[5] - X[2] * X[4];
+        cof[7] = X[2] * X[3] - X[0] * X[5];
+        cof[8] = X[0] * X[4] - X[1] * X[3];
+        // X^{-1} = cof^T / d, so X^{-+} = conj(cof) / conj(d)
+        double ad = sqrt(nrm(d));
+        double g = (it < 6) ? pow(ad, -1.0 / 3.0) : 1.0;  // scaling speeds up the first steps
+        cd dc = cj(d);
+        double dn = nrm(d);
+        double diff = 0;
+        for (int k = 0; k < 9; k++) {
+            cd inv = mk((cj(cof[k]).re * dc.re + cj(cof[k]).im * dc.im) / dn,
+                        (cj(cof[k]).im * dc.re - cj(cof[k]).re * dc.im) / dn);
+            cd nx = 0.5 * (g * X[k] + (1.0 / g) * inv);
+            diff = fmax(diff, sqrt(nrm(nx - X[k])));
+            X[k] = nx;
+        }
+        if (it >= 6 && diff < 1e-15) break;
+    }
+    cd d = det3(X);
+    double ph = atan2(d.im, d.re) / 3.0;
+    cd f = mk(cos(ph), -sin(ph));
+    for (int k = 0; k < 9; k++) W[k] = f * X[k];
+}
+
+struct Geo3 {
+    int L[4];
+    long st[4];
+};
+
+__device__ __forceinline__ long nbr(const Geo3& g, long s, int x, int mu, int d) {
+    int xm = x + d;
+    if (xm < 0) return s + (long)(g.L[mu] - 1) * g.st[mu];
+    if (xm >= g.L[mu]) return s - (long)(g.L[mu] - 1) * g.st[mu];
+    return s + d * g.st[mu];
+}
+
+__device__ __forceinline__ void coords(const Geo3& g, long s, int* x) {
+    long r = s;
+    x[0] = r % g.L[0]; r /= g.L[0];
+    x[1] = r % g.L[1]; r /= g.L[1];
+    x[2] = r % g.L[2]; r /= g.L[2];
+    x[3] = (int)r;
+}
+
+__device__ __forceinline__ void ldU(const double2* U, long V, int mu, long s, cd* u) {
+    for (int k = 0; k < 9; k++) {
+        double2 v = U[((long)mu * 9 + k) * V + s];
+        u[k] = mk(v.x, v.y);
+    }
+}
+
+// one APE step on the spatial links (all updated from the previous links)
+__global__ void k_ape(const double2* __restrict__ Uin, double2* __restrict__ Uout, Geo3 g, long V, double alpha) {
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    int x[4];
+    coords(g, s, x);
+    for (int k = 0; k < 3; k++) {
+        cd M[9], Uk[9], S[9];
+        ldU(Uin, V, k, s, Uk);
+        for (int q = 0; q < 9; q++) S[q] = mk(0.0, 0.0);
+        for (int j = 0; j < 3; j++) {
+            if (j == k) continue;
+            cd a[9], b[9], c[9], t1[9], t2[9];
+            long sj = nbr(g, s, x[j], j, 1), sk = nbr(g, s, x[k], k, 1);
+            // up: U_j(x) U_k(x+j) U_j(x+k)^+
+            ldU(Uin, V, j, s, a);
+            ldU(Uin, V, k, sj, b);
+            ldU(Uin, V, j, sk, c);
+            m3mul(a, b, t1);
+            m3mul(t1, c, t2, false, true);
+            for (int q = 0; q < 9; q++) S[q] = S[q] + t2[q];
+            // down: U_j(x-j)^+ U_k(x-j) U_j(x-j+k)
+            long sjm = nbr(g, s, x[j], j, -1);
+            int xk = x[k];
+            long sjmk = nbr(g, sjm, xk, k, 1);
+            ldU(Uin, V, j, sjm, a);
+            ldU(Uin, V, k, sjm, b);
+            ldU(Uin, V, j, sjmk, c);
+            m3mul(a, b, t1, true, false);
+            m3mul(t1, c, t2);
+            for (int q = 0; q < 9; q++) S[q] = S[q] + t2[q];
+        }
+        for (int q = 0; q < 9; q++) M[q] = (1.0 - alpha) * Uk[q] + (alpha / 4.0) * S[q];
+        cd W[9];
+        su3_project(M, W);
+        for (int q = 0; q < 9; q++) Uout[((long)k * 9 + q) * V + s] = make_double2(W[q].re, W[q].im);
+    }
+}
+
+// smeared spatial links -> canonical [s][mu][a][b] with the time link copied
+__global__ void k_smeared_export(const double2* __restrict__ Usm, const double2* __restrict__ U64, long V,
+                                 double2* __restrict__ out) {
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    for (int mu = 0; mu < 4; mu++)
+        for (int q = 0; q < 9; q++)
+            out[(s * 4 + mu) * 9 + q] = mu < 3 ? Usm[((long)mu * 9 + q) * V + s] : U64[((long)3 * 9 + q) * V + s];
+}
+
+// ------------------------------------------------------------------ 3-D Laplacian on eigenvector blocks
+// y[t][xs*3+c][j] = sum_k [2 y(x) - U_k(x) y(x+k) - U_k(x-k)^+ y(x-k)]  (within timeslice t)
+__global__ void k_laplace(const double2* __restrict__ U, const double2* __restrict__ in, double2* __restrict__ out,
+                          Geo3 g, long V, int m) {
+    const long tot = V * m;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long s = i / m;
+        const int j = (int)(i - s * m);
+        int x[4];
+        coords(g, s, x);
+        cd acc[3];
+        for (int c = 0; c < 3; c++) {
+            double2 v = in[(s * 3 + c) * m + j];
+            acc[c] = mk(6.0 * v.x, 6.0 * v.y);
+        }
+        for (int k = 0; k < 3; k++) {
+            long sf = nbr(g, s, x[k], k, 1), sb = nbr(g, s, x[k], k, -1);
+            cd u[9], yf[3], yb[3];
+            for (int c = 0; c < 3; c++) {
+                double2 a = in[(sf * 3 + c) * m + j], b = in[(sb * 3 + c) * m + j];
+                yf[c] = mk(a.x, a.y);
+                yb[c] = mk(b.x, b.y);
+            }
+            ldU(U, V, k, s, u);
+            for (int a = 0; a < 3; a++) acc[a] = acc[a] - (u[a * 3] * yf[0] + u[a * 3 + 1] * yf[1] + u[a * 3 + 2] * yf[2]);
+            ldU(U, V, k, sb, u);
+            for (int a = 0; a < 3; a++)
+                acc[a] = acc[a] - (cjmul(u[a], yb[0]) + cjmul(u[3 + a], yb[1]) + cjmul(u[6 + a], yb[2]));
+        }
+        for (int c = 0; c < 3; c++) out[(s * 3 + c) * m + j] = make_double2(acc[c].re, acc[c].im);
+    }
+}
+
+// Chebyshev step: out = a * (L y - c y) + b * prev   (L y given in ly)
+__global__ void k_cheb(const double2* __restrict__ ly, const double2* __restrict__ y, const double2* __restrict__ prev,
+                       double2* __restrict__ out, long n, double a, double c, double b) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double2 l = ly[i], v = y[i];
+        double2 p = prev ? prev[i] : make_double2(0, 0);
+        out[i] = make_double2(a * (l.x - c * v.x) + b * p.x, a * (l.y - c * v.y) + b * p.y);
+    }
+}
+
+// deterministic pseudo-random start vectors (splitmix64 of the element index)
+__global__ void k_rand_fill(double2* y, long n, unsigned long long seed) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        unsigned long long z = seed + 0x9e3779b97f4a7c15ULL * (unsigned long long)(2 * i + 1);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z = z ^ (z >> 31);
+        double a = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        z += 0x9e3779b97f4a7c15ULL;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z = z ^ (z >> 31);
+        double b = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        y[i] = make_double2(a, b);
+    }
+}
+
+// ------------------------------------------------------------------ FP64 MFMA contractions
+// Partial tiles of C_b = A_b^H B_b with A_b (K x M), B_b (K x N) row-major
+// complex (element (k,i) at A + b*sA + k*lda + i).  One wavefront computes one
+// 16x16 output tile over one K-chunk with v_mfma_f64_16x16x4f64; the complex
+// product is four real products.  Partials go to P[b][ks][M][N].
+__global__ __launch_bounds__(64) void k_zgemm_hn(const double2* __restrict__ A, long lda, long sA,
+                                                 const double2* __restrict__ B, long ldb, long sB,
+                                                 double2* __restrict__ P, int M, int N, int K, int kchunk, int nks,
+                                                 int tilesM, int tilesN) {
+    const int lane = threadIdx.x;
+    int w = blockIdx.x;
+    const int tj = w % tilesN; w /= tilesN;
+    const int ti = w % tilesM; w /= tilesM;
+    const int ks = w % nks; w /= nks;
+    const int b = w;
+    const int i = ti * 16 + (lane & 15);
+    const int j = tj * 16 + (lane & 15);
+    const int kq = lane >> 4;
+    const double2* Ab = A + (long)b * sA;
+    const double2* Bb = B + (long)b * sB;
+    d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int k0 = ks * kchunk, k1 = min(K, k0 + kchunk);
+    for (int kb = k0; kb < k1; kb += 4) {
+        const int k = kb + kq;
+        double2 a = (k < k1 && i < M) ? Ab[(long)k * lda + i] : make_double2(0, 0);
+        double2 v = (k < k1 && j < N) ? Bb[(long)k * ldb + j] : make_double2(0, 0);
+        // conj(a) * v = (ar br + ai bi) + i (ar bi - ai br)
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, v.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, v.x, ci, 0, 0, 0);
+    }
+    // accumulator layout of v_mfma_f64_16x16x4f64: register e of a lane holds
+    // row lane/16 + 4e, column lane%16
+    for (int e = 0; e < 4; e++) {
+        const int row = ti * 16 + (lane >> 4) + 4 * e;
+        const int col = tj * 16 + (lane & 15);
+        if (row < M && col < N) P[(((long)b * nks + ks) * M + row) * N + col] = make_double2(cr[e], ci[e]);
+    }
+}
+
+// C[b][i][j] = sum_ks P[b][ks][i][j] (fixed order)
+__global__ void k_ksum(const double2* __restrict__ P, double2* __restrict__ C, int M, int N, int nks, int batch) {
+    long tot = (long)batch * M * N;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        long b = q / ((long)M * N), e = q - b * M * N;
+        double re = 0, im = 0;
+        for (int ks = 0; ks < nks; ks++) {
+            double2 v = P[((long)b * nks + ks) * M * N + e];
+            re += v.x;
+            im += v.y;
+        }
+        C[q] = make_double2(re, im);
+    }
+}
+
+// Y_b (K x m) <- Y_b C_b (C_b m x m) on MFMA: one wavefront per 16x16 output tile.
+__global__ __launch_bounds__(64) void k_zgemm_nn(const double2* __restrict__ Y, const double2* __restrict__ Cm,
+                                                 double2* __restrict__ out, int K, int m, int tilesK, int tilesM) {
+    const int lane = threadIdx.x;
+    int w = blockIdx.x;
+    const int tj = w % tilesM; w /= tilesM;
+    const int tr = w % tilesK; w /= tilesK;
+    const int b = w;
+    const int row = tr * 16 + (lane & 15);
+    const int col = tj * 16 + (lane & 15);
+    const int kq = lane >> 4;
+    const double2* Yb = Y + (long)b * K * m;
+    const double2* Cb = Cm + (long)b * m * m;
+    d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    for (int kb = 0; kb < m; kb += 4) {
+        const int k = kb + kq;
+        double2 a = (k < m && row < K) ? Yb[(long)row * m + k] : make_double2(0, 0);
+        double2 v = (k < m && col < m) ? Cb[(long)k * m + col] : make_double2(0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, v.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, v.x, ci, 0, 0, 0);
+    }
+    for (int e = 0; e < 4; e++) {
+        const int r = tr * 16 + (lane >> 4) + 4 * e;
+        const int c = tj * 16 + (lane & 15);
+        if (r < K && c < m) out[((long)b * K + r) * m + c] = make_double2(cr[e], ci[e]);
+    }
+}
+
+// per (t, j): ||L y_j - lambda_j y_j||^2 for the first nv columns
+__global__ void k_resid(const double2* __restrict__ ly, const double2* __restrict__ y, const double* __restrict__ lam,
+                        double* __restrict__ out, int K, int m, int nv) {
+    const int t = blockIdx.y;
+    const int j = blockIdx.x;
+    if (j >= nv) return;
+    const double l = lam[t * m + j];
+    double acc[1] = {0};
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        double2 a = ly[((long)t * K + k) * m + j], b = y[((long)t * K + k) * m + j];
+        double re = a.x - l * b.x, im = a.y - l * b.y;
+        acc[0] += re * re + im * im;
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0) out[t * nv + j] = acc[0];
+}
+
+// internal [t][xs*3+c][j] (first nv of m columns) -> canonical V[t][i][xs][c]
+__global__ void k_eig_export(const double2* __restrict__ Y, double2* __restrict__ V, int T, long K, int m, int nv) {
+    long tot = (long)T * nv * K;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        long t = q / (nv * K), r = q - t * nv * K;
+        long i = r / K, k = r - i * K;
+        V[q] = Y[((long)t * K + k) * m + i];
+    }
+}
+
+// canonical V[t][i][xs][c] -> internal [t][xs*3+c][i]
+__global__ void k_eig_import(const double2* __restrict__ V, double2* __restrict__ Y, int T, long K, int nv) {
+    long tot = (long)T * nv * K;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        long t = q / (nv * K), r = q - t * nv * K;
+        long i = r / K, k = r - i * K;
+        Y[((long)t * K + k) * nv + i] = V[q];
+    }
+}
+
+// ------------------------------------------------------------------ sources, slabs, loops
+struct SrcSpec {
+    unsigned long long tmask;  // source timeslices (bit t), up to 64
+    int i, alpha;
+};
+
+// eta_r(x) = sum_{t in tmask_r} delta_{x4,t} v_i(t; xs) (x) e_alpha, native FP64 [12][V][n]
+__global__ void k_sources(const double2* __restrict__ Vi /* [t][xs*3+c][nv] */, const SrcSpec* __restrict__ spec,
+                          double2* __restrict__ out, long V, long Vs, int nv, int n) {
+    const long tot = V * n;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        const long s = q / n;
+        const int r = (int)(q - s * n);
+        const long t = s / Vs, xs = s - t * Vs;
+        const SrcSpec sp = spec[r];
+        const bool on = (sp.tmask >> t) & 1ULL;
+        for (int k = 0; k < 12; k++) {
+            const int a = k / 3, c = k % 3;
+            double2 v = make_double2(0, 0);
+            if (on && a == sp.alpha) v = Vi[((t * Vs + xs) * 3 + c) * nv + sp.i];
+            out[((long)k * V + s) * n + r] = v;
+        }
+    }
+}
+
+// slab gather at sink timeslice t: native FP64 X [12][V][n] -> G[xs*3+c][beta*n + r]
+__global__ void k_slab(const double2* __restrict__ X, double2* __restrict__ G, long V, long Vs, int n, int t) {
+    const long tot = Vs * 12 * n;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        const long xs = q / (12 * n);
+        const int rem = (int)(q - xs * 12 * n);
+        const int c = rem / (4 * n);
+        const int rem2 = rem - c * 4 * n;  // beta*n + r
+        const int beta = rem2 / n, r = rem2 - beta * n;
+        const long s = (long)t * Vs + xs;
+        G[(xs * 3 + c) * (4L * n) + rem2] = X[((long)(beta * 3 + c) * V + s) * n + r];
+    }
+}
+
+// tau_all[t][j][beta][i][alpha] <- C[j][beta*n + r] for the batch's (i_r, alpha_r)
+__global__ void k_tau_scatter(const double2* __restrict__ C, const SrcSpec* __restrict__ spec, double2* __restrict__ tau,
+                              int nv, int n, int t) {
+    const int tot = nv * 4 * n;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        const int j = q / (4 * n), rem = q - j * 4 * n;
+        const int beta = rem / n, r = rem - beta * n;
+        const int i = spec[r].i, a = spec[r].alpha;
+        tau[((((long)t * nv + j) * 4 + beta) * nv + i) * 4 + a] = C[(long)j * 4 * n + rem];
+    }
+}
+
+// tau[snk][j][beta][r] from C (perambulator entry point)
+__global__ void k_tau_store(const double2* __restrict__ C, double2* __restrict__ tau, int nv, int n, int snk) {
+    const int tot = nv * 4 * n;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x)
+        tau[(long)snk * tot + q] = C[q];
+}
+
+// Dirac matrices of the loop channels (chiral basis), entries in {0, +-1, +-i}:
+// G(g)[a][b] as (re, im).  Built from the defining products, not typed per channel.
+__device__ __forceinline__ cd gamma_entry(int mu, int a, int b) {
+    // mu 0..2: gamma_k = [[0, -i s_k], [i s_k, 0]]; mu 3: [[0, 1], [1, 0]]
+    const bool up = a < 2, bu = b < 2;
+    if (up == bu) return mk(0.0, 0.0);
+    const int p = a & 1, q = b & 1;
+    if (mu == 3) return p == q ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    cd s;  // Pauli sigma_{mu+1}[p][q]
+    if (mu == 0) s = (p != q) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    else if (mu == 1) s = (p == q) ? mk(0.0, 0.0) : (p == 0 ? mk(0.0, -1.0) : mk(0.0, 1.0));
+    else s = (p != q) ? mk(0.0, 0.0) : (p == 0 ? mk(1.0, 0.0) : mk(-1.0, 0.0));
+    return up ? neg(ti(s)) : ti(s);
+}
+
+__device__ __forceinline__ cd channel_entry(int g, int a, int b) {
+    if (g == DISCO_G_1) return a == b ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    if (g == DISCO_G_5) return a == b ? mk(a < 2 ? 1.0 : -1.0, 0.0) : mk(0.0, 0.0);
+    return gamma_entry(g - DISCO_G_X, a, b);
+}
+
+// L[g][t] = sum_i w[t][i] sum_{a,b} Gamma_ab tau[t][i][b][i][a]
+__global__ void k_loops(const double2* __restrict__ tau, int T, int nv, const double* __restrict__ w,
+                        const int* __restrict__ gam, int ng, double2* __restrict__ L) {
+    const int g = blockIdx.x / T, t = blockIdx.x % T;
+    double acc[2] = {0, 0};
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const double wi = w ? w[(long)t * nv + i] : 1.0;
+        cd s = mk(0.0, 0.0);
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                cd G = channel_entry(gam[g], a, b);
+                if (G.re == 0 && G.im == 0) continue;
+                double2 v = tau[((((long)t * nv + i) * 4 + b) * nv + i) * 4 + a];
+                s = s + G * mk(v.x, v.y);
+            }
+        acc[0] += wi * s.re;
+        acc[1] += wi * s.im;
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0) L[(long)g * T + t] = make_double2(acc[0], acc[1]);
+}
+
+// Correlator of loops La, Lb [ncfg][T]: C(dt) = mean_{y0} [mean_c La(y0+dt) Lb(y0) - VEV]
+__device__ cd corr_one(const double2* La, const double2* Lb, int ncfg, int T, const int* y0s, int ny0, int vev_mode,
+                       int dt) {
+    cd acc = mk(0.0, 0.0);
+    cd ma_all = mk(0.0, 0.0), mb_all = mk(0.0, 0.0);
+    if (vev_mode == 1) {
+        for (int c = 0; c < ncfg; c++)
+            for (int t = 0; t < T; t++) {
+                ma_all = ma_all + mk(La[c * T + t].x, La[c * T + t].y);
+                mb_all = mb_all + mk(Lb[c * T + t].x, Lb[c * T + t].y);
+            }
+        ma_all = (1.0 / (ncfg * T)) * ma_all;
+        mb_all = (1.0 / (ncfg * T)) * mb_all;
+    }
+    for (int k = 0; k < ny0; k++) {
+        const int y0 = y0s[k], x0 = (y0 + dt) % T;
+        cd two = mk(0.0, 0.0), ma = mk(0.0, 0.0), mb = mk(0.0, 0.0);
+        for (int c = 0; c < ncfg; c++) {
+            cd a = mk(La[c * T + x0].x, La[c * T + x0].y), b = mk(Lb[c * T + y0].x, Lb[c * T + y0].y);
+            two = two + a * b;
+            ma = ma + a;
+            mb = mb + b;
+        }
+        two = (1.0 / ncfg) * two;
+        cd vev = vev_mode == 0 ? ((1.0 / ncfg) * ma) * ((1.0 / ncfg) * mb) : ma_all * mb_all;
+        acc = acc + (two - vev);
+    }
+    return (1.0 / ny0) * acc;
+}
+
+// one thread per (term, dt); terms: 0 full, 1 factorised (= block-block), 2 block-delta,
+// 3 delta-block, 4 delta-delta, with delta L = L_full - L_blk computed into dl/dlt.
+__global__ void k_correlator(const double2* Lf, const double2* Ltf, const double2* Lb, const double2* Ltb,
+                             const double2* dl, const double2* dlt, int ncfg, int T, const int* y0s, int ny0,
+                             int vev_mode, double2* out /* [5][T] */) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 5 * T) return;
+    const int term = q / T, dt = q % T;
+    const double2* A[5] = {Lf, Lb, Lb, dl, dl};
+    const double2* B[5] = {Ltf, Ltb, dlt, Ltb, dlt};
+    cd c = corr_one(A[term], B[term], ncfg, T, y0s, ny0, vev_mode, dt);
+    out[q] = make_double2(c.re, c.im);
+}
+
+__global__ void k_sub(const double2* a, const double2* b, double2* c, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        c[i] = make_double2(a[i].x - b[i].x, a[i].y - b[i].y);
+}
+
+// dir 0: [nvec][R] -> [R][nvec]; dir 1: the inverse (R rows of colour-vector entries)
+__global__ void k_blk_transpose(const double2* __restrict__ src, double2* __restrict__ dst, int nvec, long R, int dir) {
+    long tot = (long)nvec * R;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        long i = q / R, r = q - i * R;
+        if (dir == 0) dst[r * nvec + i] = src[q];
+        else dst[q] = src[r * nvec + i];
+    }
+}
+
+static int grid_for(long n, int bs = 256, int cap = 8192) { return (int)std::max(1L, std::min<long>((n + bs - 1) / bs, cap)); }
+
+Geo3 geo_of(disco_ctx* ctx) {
+    Geo3 g;
+    long st = 1;
+    for (int m = 0; m < 4; m++) {
+        g.L[m] = ctx->dims[m];
+        g.st[m] = st;
+        st *= ctx->dims[m];
+    }
+    return g;
+}
+
+// C_b = A_b^H B_b for a batch (device), M x N outputs
+void zgemm_hn(disco_ctx* ctx, const double2* A, long lda, long sA, const double2* B, long ldb, long sB, double2* C,
+              int M, int N, int K, int batch) {
+    const int tilesM = (M + 15) / 16, tilesN = (N + 15) / 16;
+    // split K so that the launch has a few thousand wavefronts
+    long tiles = (long)tilesM * tilesN * batch;
+    int nks = (int)std::max(1L, std::min<long>(4096 / std::max(1L, tiles), (K + 63) / 64));
+    int kchunk = ((K + nks - 1) / nks + 3) / 4 * 4;
+    nks = (K + kchunk - 1) / kchunk;
+    double2* P = (double2*)ws_get(ctx, "gemm_part", sizeof(double2) * (size_t)batch * nks * M * N);
+    int rec = prof_begin(ctx);
+    hipLaunchKernelGGL(k_zgemm_hn, dim3((unsigned)(tiles * nks)), dim3(64), 0, ctx->stream, A, lda, sA, B, ldb, sB, P,
+                       M, N, K, kchunk, nks, tilesM, tilesN);
+    HIPCHK(hipGetLastError());
+    prof_end(ctx, rec, 1, 8.0 * M * N * (double)K * batch /* flop, recorded in the bytes slot */);
+    k_ksum<<<grid_for((long)batch * M * N), 256, 0, ctx->stream>>>(P, C, M, N, nks, batch);
+    HIPCHK(hipGetLastError());
+}
+
+void zgemm_nn(disco_ctx* ctx, const double2* Y, const double2* Cm, double2* out, int K, int m, int batch) {
+    const int tilesK = (K + 15) / 16, tilesM = (m + 15) / 16;
+    hipLaunchKernelGGL(k_zgemm_nn, dim3((unsigned)((long)tilesK * tilesM * batch)), dim3(64), 0, ctx->stream, Y, Cm,
+                       out, K, m, tilesK, tilesM);
+    HIPCHK(hipGetLastError());
+}
+
+// Batched Rayleigh-Ritz on the host for T timeslices: given G = Y^H Y and
+// H = Y^H L Y (m x m each), return C with Y C orthonormal Ritz vectors and
+// the Ritz values.  Falls back to an identity-regularised Cholesky if G is
+// numerically singular.
+bool rayleigh_ritz(int T, int m, const std::vector<dense::zc>& G, const std::vector<dense::zc>& H,
+                   std::vector<dense::zc>& C, std::vector<double>& lam) {
+    C.assign((size_t)T * m * m, 0.0);
+    lam.assign((size_t)T * m, 0.0);
+    bool ok = true;
+    auto work = [&](int t0, int t1) {
+        std::vector<dense::zc> R(m * m), Ri(m * m), Hp(m * m), tmp(m * m), Z(m * m);
+        for (int t = t0; t < t1; t++) {
+            const dense::zc* g = &G[(size_t)t * m * m];
+            const dense::zc* h = &H[(size_t)t * m * m];
+            if (!dense::cholesky_upper(g, R.data(), m)) {
+                ok = false;
+                continue;
+            }
+            dense::inv_upper(R.data(), Ri.data(), m);
+            // H' = R^{-H} H R^{-1}
+            dense::matmul(h, Ri.data(), tmp.data(), m);
+            for (int i = 0; i < m; i++)
+                for (int j = 0; j < m; j++) {
+                    dense::zc s = 0;
+                    for (int k = 0; k < m; k++) s += std::conj(Ri[k * m + i]) * tmp[k * m + j];
+                    Hp[i * m + j] = s;
+                }
+            for (int i = 0; i < m; i++)
+                for (int j = i; j < m; j++) {
+                    dense::zc a = 0.5 * (Hp[i * m + j] + std::conj(Hp[j * m + i]));
+                    Hp[i * m + j] = a;
+                    Hp[j * m + i] = std::conj(a);
+                }
+            dense::eigh_jacobi(Hp.data(), &lam[(size_t)t * m], Z.data(), m);
+            dense::matmul(Ri.data(), Z.data(), &C[(size_t)t * m * m], m);
+        }
+    };
+    int nth = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    nth = std::min(nth, T);
+    std::vector<std::thread> th;
+    for (int k = 0; k < nth; k++) th.emplace_back(work, T * k / nth, T * (k + 1) / nth);
+    for (auto& x : th) x.join();
+    return ok;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int disco_ape_smear(disco_ctx* ctx, int steps, double alpha) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(ctx->have_gauge, DISCO_ESTATE, "ape_smear before gauge_set");
+        REQUIRE(steps >= 0, DISCO_EINVAL, "steps < 0");
+        activate(ctx);
+        const long V = ctx->V;
+        if (!ctx->Usm) HIPCHK(hipMalloc(&ctx->Usm, sizeof(double2) * 27 * V));
+        double2* tmp = (double2*)ws_get(ctx, "ape_tmp", sizeof(double2) * 36 * V);
+        // start: spatial links of U (the time link slot of tmp mirrors U64 for the staple reads)
+        HIPCHK(hipMemcpyAsync(ctx->Usm, ctx->U64, sizeof(double2) * 27 * V, hipMemcpyDeviceToDevice, ctx->stream));
+        Geo3 g = geo_of(ctx);
+        for (int k = 0; k < steps; k++) {
+            k_ape<<<grid_for(V, 128, 1 << 30), 128, 0, ctx->stream>>>(ctx->Usm, tmp, g, V, alpha);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(ctx->Usm, tmp, sizeof(double2) * 27 * V, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        ctx->have_smeared = true;
+    });
+}
+
+int disco_smeared_get(disco_ctx* ctx, void* U_out) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(ctx->have_smeared, DISCO_ESTATE, "no smeared links");
+        REQUIRE(U_out, DISCO_EINVAL, "NULL output");
+        activate(ctx);
+        k_smeared_export<<<grid_for(ctx->V, 256, 1 << 30), 256, 0, ctx->stream>>>(ctx->Usm, ctx->U64, ctx->V,
+                                                                                 (double2*)U_out);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int disco_laplace_apply(disco_ctx* ctx, int nvec, const void* in, void* out) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(ctx->have_gauge, DISCO_ESTATE, "laplace before gauge_set");
+        REQUIRE(in && out && nvec > 0, DISCO_EINVAL, "bad argument");
+        activate(ctx);
+        const long V = ctx->V;
+        const double2* U = ctx->have_smeared ? ctx->Usm : ctx->U64;
+        // canonical [nvec][V][3] -> internal [V*3][nvec] (T blocks of K rows are contiguous)
+        const int T = ctx->dims[3];
+        const long K = 3 * ctx->Vs;
+        double2* a = (double2*)ws_get(ctx, "lap_a", sizeof(double2) * V * 3 * nvec);
+        double2* b = (double2*)ws_get(ctx, "lap_b", sizeof(double2) * V * 3 * nvec);
+        k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>((const double2*)in, a, nvec, T * K, 0);
+        k_laplace<<<grid_for(V * nvec), 256, 0, ctx->stream>>>(U, a, b, geo_of(ctx), V, nvec);
+        k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>(b, (double2*)out, nvec, T * K, 1);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vout, double* lambda) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(ctx->have_gauge, DISCO_ESTATE, "laplace_eigvecs before gauge_set");
+        REQUIRE(Vout && lambda, DISCO_EINVAL, "NULL output");
+        const int T = ctx->dims[3];
+        const long Vs = ctx->Vs, V = ctx->V, K = 3 * Vs;
+        REQUIRE(nv >= 1 && nv <= K, DISCO_EINVAL, "nv %d out of range 1..%ld", nv, K);
+        activate(ctx);
+        const double2* U = ctx->have_smeared ? ctx->Usm : ctx->U64;
+        const int guard = std::max(4, nv / 4);
+        int m = (int)std::min<long>(K, ((nv + guard + 3) / 4) * 4);
+        if (m > K) m = (int)K;
+        const size_t nY = (size_t)T * K * m;
+        double2* Y = (double2*)ws_get(ctx, "eig_Y", sizeof(double2) * nY);
+        double2* LY = (double2*)ws_get(ctx, "eig_LY", sizeof(double2) * nY);
+        double2* Y1 = (double2*)ws_get(ctx, "eig_Y1", sizeof(double2) * nY);
+        double2* Y2 = (double2*)ws_get(ctx, "eig_Y2", sizeof(double2) * nY);
+        double2* Gd = (double2*)ws_get(ctx, "eig_G", sizeof(double2) * T * m * m);
+        double2* Cd = (double2*)ws_get(ctx, "eig_C", sizeof(double2) * T * m * m);
+        double* lamd = (double*)ws_get(ctx, "eig_lam", sizeof(double) * T * m);
+        double* resd = (double*)ws_get(ctx, "eig_res", sizeof(double) * T * nv);
+        Geo3 g = geo_of(ctx);
+        const int gY = grid_for((long)nY);
+        k_rand_fill<<<gY, 256, 0, ctx->stream>>>(Y, (long)nY, 0x5eed1234ULL);
+        std::vector<dense::zc> Gh((size_t)T * m * m), Hh((size_t)T * m * m), Ch;
+        std::vector<double> lam, res((size_t)T * nv);
+        auto lap = [&](const double2* in, double2* out) {
+            k_laplace<<<grid_for(V * m), 256, 0, ctx->stream>>>(U, in, out, g, V, m);
+            HIPCHK(hipGetLastError());
+        };
+        auto gram = [&](const double2* A, const double2* B, std::vector<dense::zc>& host) {
+            zgemm_hn(ctx, A, m, K * m, B, m, K * m, Gd, m, m, (int)K, T);
+            HIPCHK(hipMemcpyAsync(host.data(), Gd, sizeof(double2) * T * m * m, hipMemcpyDeviceToHost, ctx->stream));
+        };
+        // Rayleigh-Ritz on the current Y (not necessarily orthonormal): Y <- Y C, LY <- L Y C
+        auto rr = [&]() {
+            lap(Y, LY);
+            gram(Y, Y, Gh);
+            gram(Y, LY, Hh);
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            bool ok = rayleigh_ritz(T, m, Gh, Hh, Ch, lam);
+            REQUIRE(ok, DISCO_EINVAL, "eigensolver: Gram matrix not positive definite");
+            HIPCHK(hipMemcpyAsync(Cd, Ch.data(), sizeof(double2) * T * m * m, hipMemcpyHostToDevice, ctx->stream));
+            zgemm_nn(ctx, Y, Cd, Y1, (int)K, m, T);
+            zgemm_nn(ctx, LY, Cd, Y2, (int)K, m, T);
+            std::swap(Y, Y1);
+            std::swap(LY, Y2);
+            HIPCHK(hipMemcpyAsync(lamd, lam.data(), sizeof(double) * T * m, hipMemcpyHostToDevice, ctx->stream));
+            k_resid<<<dim3(nv, T), 256, 0, ctx->stream>>>(LY, Y, lamd, resd, (int)K, m, nv);
+            HIPCHK(hipMemcpyAsync(res.data(), resd, sizeof(double) * T * nv, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            double worst = 0;
+            for (double v : res) worst = std::max(worst, std::sqrt(v));
+            return worst;
+        };
+        double worst = rr();
+        const double upper = 12.0;  // spectrum of -Delta lies in [0, 12]
+        const int degree = 12;
+        const double want = tol > 0 ? tol : 1e-12;
+        for (int it = 0; it < 400 && worst > want; it++) {
+            // Chebyshev filter damping [a, upper], a = largest current Ritz value over the slices
+            double a = 0;
+            for (int t = 0; t < T; t++) a = std::max(a, lam[(size_t)t * m + m - 1]);
+            a = std::min(a, 0.9 * upper);
+            const double e = (upper - a) / 2, c = (upper + a) / 2;
+            // T1 = (L - c) Y / e ; T_{k+1} = 2 (L - c) T_k / e - T_{k-1}
+            lap(Y, LY);
+            k_cheb<<<gY, 256, 0, ctx->stream>>>(LY, Y, nullptr, Y1, (long)nY, 1.0 / e, c, 0.0);
+            double2 *prev = Y, *cur = Y1, *nxt = Y2;
+            for (int k = 1; k < degree; k++) {
+                lap(cur, LY);
+                k_cheb<<<gY, 256, 0, ctx->stream>>>(LY, cur, prev, nxt, (long)nY, 2.0 / e, c, -1.0);
+                double2* t0 = prev;
+                prev = cur;
+                cur = nxt;
+                nxt = t0;
+            }
+            if (cur != Y) HIPCHK(hipMemcpyAsync(Y, cur, sizeof(double2) * nY, hipMemcpyDeviceToDevice, ctx->stream));
+            // re-orthonormalise before the Ritz step (Cholesky QR), then Rayleigh-Ritz
+            gram(Y, Y, Gh);
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            {
+                std::vector<dense::zc> R(m * m), Ri((size_t)T * m * m);
+                for (int t = 0; t < T; t++) {
+                    // scale-aware: normalise the columns first to keep Cholesky well conditioned
+                    bool ok = dense::cholesky_upper(&Gh[(size_t)t * m * m], R.data(), m);
+                    REQUIRE(ok, DISCO_EINVAL, "eigensolver: filtered block lost rank");
+                    dense::inv_upper(R.data(), &Ri[(size_t)t * m * m], m);
+                }
+                HIPCHK(hipMemcpyAsync(Cd, Ri.data(), sizeof(double2) * T * m * m, hipMemcpyHostToDevice, ctx->stream));
+                zgemm_nn(ctx, Y, Cd, Y1, (int)K, m, T);
+                std::swap(Y, Y1);
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+            }
+            worst = rr();
+        }
+        // the swaps may have moved the final block into another workspace buffer
+        ctx->ws["eig_Y"].first = Y;
+        ctx->ws["eig_Y1"].first = Y1;
+        ctx->ws["eig_LY"].first = LY;
+        ctx->ws["eig_Y2"].first = Y2;
+        REQUIRE(worst <= want, DISCO_ENOCONV, "eigensolver: residual %.3e above %.3e", worst, want);
+        k_eig_export<<<grid_for((long)T * nv * K), 256, 0, ctx->stream>>>(Y, (double2*)Vout, T, K, m, nv);
+        HIPCHK(hipGetLastError());
+        for (int t = 0; t < T; t++)
+            for (int i = 0; i < nv; i++) lambda[(size_t)t * nv + i] = lam[(size_t)t * m + i];
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int disco_perambulator(disco_ctx* ctx, const void* Vin, int nv, int nsrc, const void* X, const int* t_snk, int n_snk,
+                       void* tau) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(Vin && X && t_snk && tau && nv > 0 && nsrc > 0 && n_snk > 0, DISCO_EINVAL, "bad argument");
+        REQUIRE(nsrc <= 64, DISCO_EINVAL, "at most 64 solutions per call");
+        activate(ctx);
+        const int T = ctx->dims[3];
+        const long V = ctx->V, Vs = ctx->Vs, K = 3 * Vs;
+        for (int k = 0; k < n_snk; k++) REQUIRE(t_snk[k] >= 0 && t_snk[k] < T, DISCO_EINVAL, "bad sink timeslice");
+        double2* Vi = (double2*)ws_get(ctx, "pr_V", sizeof(double2) * T * K * nv);
+        k_eig_import<<<grid_for((long)T * nv * K), 256, 0, ctx->stream>>>((const double2*)Vin, Vi, T, K, nv);
+        double2* X64 = (double2*)ws_get(ctx, "pr_X", disco::native_bytes(ctx, DISCO_F64, nsrc));
+        disco::to_native(ctx, DISCO_F64, nsrc, X, X64);
+        double2* G = (double2*)ws_get(ctx, "pr_G", sizeof(double2) * K * 4 * nsrc);
+        double2* C = (double2*)ws_get(ctx, "pr_C", sizeof(double2) * nv * 4 * nsrc);
+        for (int k = 0; k < n_snk; k++) {
+            const int t = t_snk[k];
+            k_slab<<<grid_for(Vs * 12 * nsrc), 256, 0, ctx->stream>>>(X64, G, V, Vs, nsrc, t);
+            zgemm_hn(ctx, Vi + (long)t * K * nv, nv, 0, G, 4L * nsrc, 0, C, nv, 4 * nsrc, (int)K, 1);
+            k_tau_store<<<grid_for((long)nv * 4 * nsrc), 256, 0, ctx->stream>>>(C, (double2*)tau, nv, nsrc, k);
+        }
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double* w, const int* gammas, int ngamma,
+                void* L) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(tau_tt && gammas && L && T > 0 && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
+        for (int g = 0; g < ngamma; g++) REQUIRE(gammas[g] >= 0 && gammas[g] <= 4, DISCO_EINVAL, "bad channel");
+        activate(ctx);
+        int* gd = (int*)ws_get(ctx, "lp_g", sizeof(int) * ngamma);
+        HIPCHK(hipMemcpyAsync(gd, gammas, sizeof(int) * ngamma, hipMemcpyHostToDevice, ctx->stream));
+        k_loops<<<ngamma * T, 64, 0, ctx->stream>>>((const double2*)tau_tt, T, nv, w, gd, ngamma, (double2*)L);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, const void* L_blk, const void* Lt_blk,
+                     int ncfg, int T, const int* y0_set, int ny0, int vev_mode, void* C_full, void* C_fact, void* dC,
+                     void* four_terms) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(L_full && Lt_full && L_blk && Lt_blk && C_full && C_fact && dC, DISCO_EINVAL, "NULL argument");
+        REQUIRE(ncfg >= 1 && T >= 1 && (vev_mode == 0 || vev_mode == 1), DISCO_EINVAL, "bad sizes or vev_mode");
+        activate(ctx);
+        std::vector<int> y0;
+        if (y0_set && ny0 > 0) y0.assign(y0_set, y0_set + ny0);
+        else
+            for (int t = 0; t < T; t++) y0.push_back(t);
+        for (int v : y0) REQUIRE(v >= 0 && v < T, DISCO_EINVAL, "bad source time");
+        int* yd = (int*)ws_get(ctx, "cr_y0", sizeof(int) * y0.size());
+        HIPCHK(hipMemcpyAsync(yd, y0.data(), sizeof(int) * y0.size(), hipMemcpyHostToDevice, ctx->stream));
+        const long n = (long)ncfg * T;
+        double2* dl = (double2*)ws_get(ctx, "cr_dl", sizeof(double2) * n);
+        double2* dlt = (double2*)ws_get(ctx, "cr_dlt", sizeof(double2) * n);
+        double2* out = (double2*)ws_get(ctx, "cr_out", sizeof(double2) * 5 * T);
+        k_sub<<<grid_for(n), 256, 0, ctx->stream>>>((const double2*)L_full, (const double2*)L_blk, dl, n);
+        k_sub<<<grid_for(n), 256, 0, ctx->stream>>>((const double2*)Lt_full, (const double2*)Lt_blk, dlt, n);
+        k_correlator<<<(5 * T + 63) / 64, 64, 0, ctx->stream>>>(
+            (const double2*)L_full, (const double2*)Lt_full, (const double2*)L_blk, (const double2*)Lt_blk, dl, dlt,
+            ncfg, T, yd, (int)y0.size(), vev_mode, out);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(C_full, out, sizeof(double2) * T, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(C_fact, out + T, sizeof(double2) * T, hipMemcpyDeviceToDevice, ctx->stream));
+        k_sub<<<grid_for(T), 256, 0, ctx->stream>>>(out, out + T, (double2*)dC, T);
+        if (four_terms)
+            HIPCHK(hipMemcpyAsync(four_terms, out + T, sizeof(double2) * 4 * T, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+// End-to-end distillation loops: for every timeslice (or packed set of
+// timeslices for the domain-restricted operator) and every (i, alpha), build
+// the sources, solve, project at the source timeslices, and accumulate
+// tau(t,t); then form the loops.  Solutions are never all held: only one RHS
+// block at a time.
+int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vin, int nv, const double* w,
+                        const int* gammas, int ngamma, const disco_solver_params* P, void* L, void* tau_out,
+                        disco_solver_stats* agg) {
+    if (!ctx) return DISCO_EINVAL;
+    bool all_ok = true;
+    int rc = guarded(ctx, [&] {
+        REQUIRE(Vin && gammas && P && L && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "loops before clover_setup");
+        REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
+        const int T = ctx->dims[3];
+        REQUIRE(T <= 64, DISCO_EINVAL, "at most 64 timeslices");
+        activate(ctx);
+        const long V = ctx->V, Vs = ctx->Vs, K = 3 * Vs;
+        double2* Vi = (double2*)ws_get(ctx, "ld_V", sizeof(double2) * T * K * nv);
+        k_eig_import<<<grid_for((long)T * nv * K), 256, 0, ctx->stream>>>((const double2*)Vin, Vi, T, K, nv);
+        double2* tau = tau_out ? (double2*)tau_out
+                               : (double2*)ws_get(ctx, "ld_tau", sizeof(double2) * (size_t)T * nv * 4 * nv * 4);
+        // packing sets: one timeslice per temporal layer of the partition
+        std::vector<unsigned long long> sets;
+        if (dom) {
+            const int lm = dom->lmax;
+            // temporal layers: a layer ends at every cut face along t
+            int anchor = -1;
+            for (int t = 0; t < T; t++)
+                if (dom->cut[3 * lm + t]) anchor = t;
+            if (anchor < 0) {
+                for (int t = 0; t < T; t++) sets.push_back(1ULL << t);  // one layer: nothing to pack
+            } else {
+                std::vector<std::vector<int>> layers;
+                std::vector<int> curl;
+                for (int k = 1; k <= T; k++) {
+                    const int t = (anchor + k) % T;
+                    curl.push_back(t);
+                    if (dom->cut[3 * lm + t]) {
+                        layers.push_back(curl);
+                        curl.clear();
+                    }
+                }
+                size_t maxlen = 0;
+                for (auto& l : layers) maxlen = std::max(maxlen, l.size());
+                // set p holds the p-th timeslice of every layer long enough
+                for (size_t p = 0; p < maxlen; p++) {
+                    unsigned long long msk = 0;
+                    for (auto& l : layers)
+                        if (p < l.size()) msk |= 1ULL << l[p];
+                    sets.push_back(msk);
+                }
+            }
+        } else {
+            for (int t = 0; t < T; t++) sets.push_back(1ULL << t);
+        }
+        const int nrhs_set = 4 * nv;
+        const int blk = disco::default_rhs_block(*P, nrhs_set);
+        SrcSpec* specd = (SrcSpec*)ws_get(ctx, "ld_spec", sizeof(SrcSpec) * blk);
+        double2* b64 = (double2*)ws_get(ctx, "ld_b64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* x64 = (double2*)ws_get(ctx, "ld_x64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* G = (double2*)ws_get(ctx, "ld_G", sizeof(double2) * K * 4 * blk);
+        double2* C = (double2*)ws_get(ctx, "ld_C", sizeof(double2) * nv * 4 * blk);
+        std::vector<disco_solver_stats> st(blk);
+        long long solves = 0, iters = 0;
+        double worst = 0;
+        int fb = 0, outer = 0;
+        for (unsigned long long msk : sets) {
+            for (int r0 = 0; r0 < nrhs_set; r0 += blk) {
+                const int n = std::min(blk, nrhs_set - r0);
+                std::vector<SrcSpec> spec(n);
+                for (int r = 0; r < n; r++) spec[r] = SrcSpec{msk, (r0 + r) / 4, (r0 + r) % 4};
+                HIPCHK(hipMemcpyAsync(specd, spec.data(), sizeof(SrcSpec) * n, hipMemcpyHostToDevice, ctx->stream));
+                k_sources<<<grid_for(V * n), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, n);
+                HIPCHK(hipGetLastError());
+                disco::solve_native(ctx, dom, *P, n, b64, x64, st.data());
+                for (int r = 0; r < n; r++) {
+                    all_ok &= st[r].converged != 0;
+                    worst = std::max(worst, st[r].true_rel_residual);
+                }
+                iters += st[0].iters;
+                outer += st[0].outer_iters;
+                fb |= st[0].fallback_used;
+                solves += n;
+                for (int t = 0; t < T; t++) {
+                    if (!((msk >> t) & 1ULL)) continue;
+                    k_slab<<<grid_for(Vs * 12 * n), 256, 0, ctx->stream>>>(x64, G, V, Vs, n, t);
+                    zgemm_hn(ctx, Vi + (long)t * K * nv, nv, 0, G, 4L * n, 0, C, nv, 4 * n, (int)K, 1);
+                    k_tau_scatter<<<grid_for((long)nv * 4 * n), 256, 0, ctx->stream>>>(C, specd, tau, nv, n, t);
+                }
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(ctx->stream));  // spec buffer is reused by the next block
+            }
+        }
+        int* gd = (int*)ws_get(ctx, "lp_g", sizeof(int) * ngamma);
+        HIPCHK(hipMemcpyAsync(gd, gammas, sizeof(int) * ngamma, hipMemcpyHostToDevice, ctx->stream));
+        k_loops<<<ngamma * T, 64, 0, ctx->stream>>>(tau, T, nv, w, gd, ngamma, (double2*)L);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (agg) {
+            agg->iters = (int)std::min<long long>(iters, 2147483647LL);
+            agg->outer_iters = outer;
+            agg->fallback_used = fb;
+            agg->converged = all_ok;
+            agg->true_rel_residual = worst;
+        }
+        if (agg) agg->iters = (int)std::min<long long>(iters, 2147483647LL);
+        ctx->last_solves = solves;
+    });
+    if (rc == DISCO_OK && !all_ok) {
+        ctx->err = "a distillation solve missed the tolerance";
+        return DISCO_ENOCONV;
+    }
+    return rc;
+}
+
+}  // extern "C"

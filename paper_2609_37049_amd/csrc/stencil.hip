@@ -11,6 +11,8 @@
 // skipped and the clover term is kept (D_Lambda is D restricted to the fields
 // inside each domain).  The optional epilogue fuses the Krylov reductions
 // (deterministic per-block partial sums in FP64).
+#include <algorithm>
+
 #include "spinor_io.h"
 
 namespace {
@@ -475,14 +477,18 @@ static int apply_canonical(disco_ctx* ctx, const disco_domains* dom, int prec, i
         REQUIRE(ctx->have_clover, DISCO_ESTATE, "operator applied before clover_setup");
         activate(ctx);
         if (nrhs == 0) return;
-        size_t nb = disco::native_bytes(ctx, prec, nrhs);
-        void* a = ws_get(ctx, "apply_in", nb);
-        void* b = ws_get(ctx, "apply_out", nb);
-        disco::to_native(ctx, prec, nrhs, in, a);
-        disco::StencilCall c{prec, dagger ? 1 : 0, nrhs, a, b, nullptr, nullptr, dom ? dom->d_mask : nullptr, nullptr,
-                             disco::EPI_NONE};
-        disco::stencil_launch(ctx, c);
-        disco::from_native(ctx, prec, nrhs, b, out);
+        const size_t field = (size_t)ctx->V * 12 * sizeof(double2);
+        for (int r0 = 0; r0 < nrhs; r0 += 64) {
+            const int n = std::min(64, nrhs - r0);
+            size_t nb = disco::native_bytes(ctx, prec, n);
+            void* a = ws_get(ctx, "apply_in", nb);
+            void* b = ws_get(ctx, "apply_out", nb);
+            disco::to_native(ctx, prec, n, (const char*)in + r0 * field, a);
+            disco::StencilCall c{prec, dagger ? 1 : 0, n, a, b, nullptr, nullptr, dom ? dom->d_mask : nullptr,
+                                 nullptr, disco::EPI_NONE};
+            disco::stencil_launch(ctx, c);
+            disco::from_native(ctx, prec, n, b, (char*)out + r0 * field);
+        }
     });
 }
 

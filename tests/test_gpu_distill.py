@@ -1,0 +1,287 @@
+"""GPU parity of the distillation chain against the FP64 oracle: APE smearing,
+the covariant Laplacian and its eigenpairs, the perambulator projection on
+matrix cores, loops, correlators, and end-to-end full and subtracted
+correlators (with multi-site packing of the block solves)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lattice_fixtures import unit_field, coords, momenta
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+CODES = [0, 1, 2, 3, 4]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def disco():
+    import paper_2609_37049_amd as d
+    d.lib()
+    return d
+
+
+def _ctx(disco, dims, U, kappa=None, csw=None):
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    if kappa is not None:
+        ctx.clover_setup(kappa, csw)
+    return ctx
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_ape_parity(disco):
+    dims = (4, 6, 4, 3)
+    U = synth.gauge_field(dims, 0.4, 3)
+    ctx = _ctx(disco, dims, U)
+    ctx.ape_smear(3, 0.5)
+    S = ctx.smeared_get().cpu().numpy()
+    ref = oracle.ape_smear(U, dims, 0.5, 3)
+    assert np.abs(S - ref).max() < 1e-13
+
+
+def test_laplace_apply_parity(disco):
+    dims = (5, 4, 6, 3)
+    U = synth.gauge_field(dims, 0.5, 4)
+    ctx = _ctx(disco, dims, U)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal((3, V, 3)) + 1j * rng.standard_normal((3, V, 3))
+    out = ctx.laplace_apply(ctx.dev(y)).cpu().numpy()
+    for k in range(3):
+        assert _rel(out[k], oracle.laplace(U, dims, y[k])) < 1e-14
+
+
+@pytest.mark.parametrize("dims,nv,steps", [((4, 4, 4, 4), 4, 0), ((6, 4, 4, 3), 10, 2), ((8, 8, 8, 2), 24, 1)])
+def test_eigvecs_parity(disco, dims, nv, steps):
+    _say("eigvecs", dims, nv)
+    U = synth.gauge_field(dims, 0.3, 5)
+    ctx = _ctx(disco, dims, U)
+    if steps:
+        ctx.ape_smear(steps, 0.5)
+    Us = oracle.ape_smear(U, dims, 0.5, steps) if steps else U
+    Vg, lam = ctx.laplace_eigvecs(nv, 1e-12)
+    Vg = Vg.cpu().numpy()
+    Vo, lo = oracle.laplace_eigvecs(Us, dims, nv)
+    assert np.abs(lam - lo).max() < 1e-10
+    T = dims[3]
+    Vs = Vg.shape[2]
+    for t in range(T):
+        A = Vg[t].reshape(nv, -1)
+        B = Vo[t].reshape(nv, -1)
+        assert np.abs(np.conj(A) @ A.T - np.eye(nv)).max() < 1e-12
+        # same spanned space (phases and rotations inside a cluster are free)
+        assert np.abs(A.T @ np.conj(A) - B.T @ np.conj(B)).max() < 1e-8
+
+
+def test_perambulator_parity(disco):
+    """Same V and X on both sides: tau = V^+ X at several sink timeslices (FP64 MFMA)."""
+    dims = (6, 4, 4, 5)
+    U = synth.gauge_field(dims, 0.4, 6)
+    ctx = _ctx(disco, dims, U)
+    Vo, _ = oracle.laplace_eigvecs(U, dims, 7)
+    V = int(np.prod(dims))
+    for nsrc in (1, 5, 16):
+        X = synth.random_spinor(V, nsrc, 7 + nsrc)
+        t_snk = [0, 3, 4]
+        tau = ctx.perambulator(ctx.dev(Vo), ctx.dev(X), t_snk).cpu().numpy()
+        for k, t in enumerate(t_snk):
+            ref = oracle.project(Vo, dims, X, t)
+            assert _rel(tau[k], ref) < 1e-14
+
+
+def test_loops_parity(disco):
+    rng = np.random.default_rng(8)
+    T, nv = 5, 6
+    tau = rng.standard_normal((T, nv, 4, nv, 4)) + 1j * rng.standard_normal((T, nv, 4, nv, 4))
+    w = rng.random((T, nv))
+    ctx = disco.Context((2, 2, 2, T), BC)
+    for ww in (None, w):
+        L = ctx.loops(ctx.dev(tau), CODES, None if ww is None else ctx.dev(ww)).cpu().numpy()
+        ref = oracle.loops(tau, CODES, ww)
+        assert _rel(L, ref) < 1e-14
+
+
+@pytest.mark.parametrize("vev_mode", [0, 1])
+def test_correlator_parity(disco, vev_mode):
+    rng = np.random.default_rng(9)
+    ncfg, T = 6, 8
+    mk = lambda: rng.standard_normal((ncfg, T)) + 1j * rng.standard_normal((ncfg, T))
+    Lf, Ltf = mk(), mk()
+    Lb, Ltb = Lf + 0.1 * mk(), Ltf + 0.1 * mk()
+    ctx = disco.Context((2, 2, 2, T), BC)
+    for y0s in (None, [1, 4]):
+        C, Cf, dC, four = [a.cpu().numpy() for a in ctx.correlator(ctx.dev(Lf), ctx.dev(Ltf), ctx.dev(Lb),
+                                                                    ctx.dev(Ltb), y0s, vev_mode)]
+        rC, rCf, rdC, rfour = oracle.correlator(Lf, Ltf, Lb, Ltb, y0s, vev_mode)
+        for a, b in ((C, rC), (Cf, rCf), (dC, rdC), (four, rfour)):
+            assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(rC).max())
+
+
+def _tilde_sign(code):
+    return 1.0 if code == 0 else -1.0
+
+
+@pytest.fixture(scope="module")
+def plain_oracle():
+    """Oracle loops for the plain FP64 workload (4^4, Nv=4, 2^4 domains)."""
+    pre = synth.PRESETS["plain_4x4x4x4"]
+    dims = pre.dims
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    A = oracle.clover(U, dims, pre.kappa, pre.csw)
+    Us = oracle.ape_smear(U, dims, pre.ape_alpha, pre.ape_steps) if pre.ape_steps else U
+    Vo, _ = oracle.laplace_eigvecs(Us, dims, pre.nv)
+    cut = synth.tiling_cuts(dims, pre.block)
+    T = dims[3]
+    tau_f = np.stack([oracle.perambulator_tt(U, A, dims, BC, pre.kappa, Vo, t) for t in range(T)])
+    tau_b = np.stack([oracle.perambulator_tt(U, A, dims, BC, pre.kappa, Vo, t, cut=cut) for t in range(T)])
+    return pre, U, A, Vo, cut, oracle.loops(tau_f, CODES), oracle.loops(tau_b, CODES), tau_f, tau_b
+
+
+@pytest.mark.parametrize("method", ["CGNR_F64", "BICGSTAB_DC"])
+def test_end_to_end_plain_workload(disco, plain_oracle, method):
+    """4^4 plain workload: the GPU computes its own eigenvectors, solves to 1e-12
+    (full operator and packed block solves), and its loops and full, factorised
+    and subtracted correlators agree with the oracle's to 1e-10."""
+    pre, U, A, Vo, cut, Lf_o, Lb_o, tau_f_o, tau_b_o = plain_oracle
+    dims = pre.dims
+    _say("end-to-end", method)
+    ctx = _ctx(disco, dims, U, pre.kappa, pre.csw)
+    if pre.ape_steps:
+        ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
+    Vg, _ = ctx.laplace_eigvecs(pre.nv, 1e-13)
+    dom = ctx.domains(cut)
+    P = ctx.params(method=getattr(disco, method), tol=1e-12, inner_prec=disco.F32, rhs_block=8)
+    Lf, tf, st = ctx.loops_distill(Vg, CODES, P, None, want_tau=True)
+    Lb, tb, stb = ctx.loops_distill(Vg, CODES, P, dom, want_tau=True)
+    # packing: 2 temporal layers -> half as many block solves as logical sources
+    assert ctx.last_solves() == 4 * pre.nv * dims[3] // 2
+    Lf, Lb = Lf.cpu().numpy(), Lb.cpu().numpy()
+    for g in range(len(CODES)):
+        for La, Lr in ((Lf[g], Lf_o[g]), (Lb[g], Lb_o[g])):
+            err = np.abs(La - Lr).max() / max(np.abs(Lr).max(), 1e-300)
+            assert err < 1e-10, (g, err)
+    # correlators per channel (one configuration: translation-averaged VEV)
+    for g in range(len(CODES)):
+        s = _tilde_sign(CODES[g])
+        args = [ctx.dev(v[None]) for v in (Lf[g], s * Lf[g], Lb[g], s * Lb[g])]
+        C, Cf, dC, four = [a.cpu().numpy() for a in ctx.correlator(*args)]
+        rC, rCf, rdC, _ = oracle.correlator(Lf_o[g][None], s * Lf_o[g][None], Lb_o[g][None], s * Lb_o[g][None])
+        # 1e-10 of the correlator, plus the FP64 rounding floor of the VEV-subtracted
+        # products <L Lt> - <L><Lt> (both sides hit it when C is far below |L|^2)
+        floor = 64 * np.finfo(float).eps * max(np.abs(Lf_o[g]).max(), np.abs(Lb_o[g]).max()) ** 2
+        tol = 1e-10 * np.abs(rC).max() + floor
+        assert np.abs(C - rC).max() <= tol
+        assert np.abs(Cf - rCf).max() <= tol
+        assert np.abs(dC - rdC).max() <= tol
+        assert np.abs(four.sum(axis=0) - C).max() <= floor
+
+
+def test_single_domain_block_loops_equal_full(disco):
+    dims = (4, 4, 2, 4)
+    U = synth.gauge_field(dims, 0.3, 13)
+    ctx = _ctx(disco, dims, U, 0.12, 1.0)
+    Vg, _ = ctx.laplace_eigvecs(3, 1e-12)
+    dom = ctx.domains(np.zeros((4, 4), dtype=np.uint8))
+    P = ctx.params(method=disco.CGNR_F64, tol=1e-12, rhs_block=12)
+    Lf, _, _ = ctx.loops_distill(Vg, CODES, P, None)
+    Lb, _, _ = ctx.loops_distill(Vg, CODES, P, dom)
+    assert np.abs(Lf.cpu().numpy() - Lb.cpu().numpy()).max() < 1e-10 * np.abs(Lf.cpu().numpy()).max()
+
+
+def test_uneven_domains_packing_exact(disco):
+    """Uneven temporal layers (offset tiling): packed block loops equal the
+    oracle's unpacked ones."""
+    dims = (4, 4, 4, 6)
+    U = synth.gauge_field(dims, 0.3, 14)
+    kappa, csw = 0.12, 1.2
+    ctx = _ctx(disco, dims, U, kappa, csw)
+    A = oracle.clover(U, dims, kappa, csw)
+    cut = synth.offset_tiling_cuts(dims, (4, 4, 4, 4))  # t layers of extent 2, 4 (wrapped offset)
+    dom = ctx.domains(cut)
+    Vo, _ = oracle.laplace_eigvecs(U, dims, 2)
+    P = ctx.params(method=disco.BICGSTAB_DC, tol=1e-12, rhs_block=8)
+    Lb, _, _ = ctx.loops_distill(ctx.dev(Vo), CODES, P, dom)
+    tau = np.stack([oracle.perambulator_tt(U, A, dims, BC, kappa, Vo, t, cut=cut) for t in range(dims[3])])
+    ref = oracle.loops(tau, CODES)
+    assert np.abs(Lb.cpu().numpy() - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_free_field_loops_full_size(disco):
+    """16^3 x 32 at U = 1 with plane-wave distillation vectors: the end-to-end
+    GPU loops equal the momentum-space closed form
+    L_Gamma(t) = sum_(k,c) (1/Lt) sum_p4 Tr[Gamma D(k,p4)^-1]."""
+    dims = (16, 16, 16, 32)
+    kappa = 0.12
+    _say("free field full size")
+    U = unit_field(dims)
+    ctx = _ctx(disco, dims, U, kappa, 1.0)
+    Lx, Ly, Lz, Lt = dims
+    Vs = Lx * Ly * Lz
+    X = coords(dims)[:Vs, :3]
+    ks = [(0.0, 0.0, 0.0), (2 * np.pi / 16, 0.0, 0.0), (0.0, 2 * np.pi * 3 / 16, 2 * np.pi / 16)]
+    vecs = []
+    for k in ks:
+        ph = np.exp(1j * (X @ np.asarray(k))) / np.sqrt(Vs)
+        for c in range(3):
+            v = np.zeros((Vs, 3), dtype=np.complex128)
+            v[:, c] = ph
+            vecs.append(v)
+    Vt = np.broadcast_to(np.stack(vecs), (Lt, len(vecs), Vs, 3)).copy()
+    P = ctx.params(method=disco.BICGSTAB_DC, tol=1e-11, inner_prec=disco.F32, rhs_block=12)
+    L, _, st = ctx.loops_distill(ctx.dev(Vt), CODES, P, None)
+    L = L.cpu().numpy()
+    g = [oracle.gamma(m) for m in range(4)]
+    p4s = momenta(dims, BC)[3]
+    for ci, c in enumerate(CODES):
+        gm = oracle.channel_matrix(c)
+        ref = 0j
+        for k in ks:
+            for p4 in p4s:
+                p = list(k) + [p4]
+                M = 1 - 2 * kappa * sum(np.cos(p))
+                S = (M * np.eye(4) - 2j * kappa * sum(g[m] * np.sin(p[m]) for m in range(4))) / (
+                    M ** 2 + 4 * kappa ** 2 * sum(np.sin(p) ** 2))
+                ref += 3 * np.trace(gm @ S) / len(p4s)
+        assert np.abs(L[ci] - ref).max() <= 1e-9 * max(abs(ref), 1.0), (c, L[ci][:3], ref)
+
+
+def test_full_size_eigvecs(disco):
+    """16^3 x 32 with 5 APE steps, Nv = 32: residuals, orthonormality, and the
+    eigenvalues of two timeslices against the oracle (ARPACK on its Laplacian)."""
+    pre = synth.PRESETS["prec_16x16x16x32"]
+    dims = pre.dims
+    _say("full-size eigvecs")
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    ctx = _ctx(disco, dims, U)
+    ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
+    Vg, lam = ctx.laplace_eigvecs(pre.nv, 1e-10)
+    assert np.all(np.diff(lam, axis=1) >= -1e-12)
+    Us = ctx.smeared_get().cpu().numpy()
+    Uo = oracle.ape_smear(U, dims, pre.ape_alpha, pre.ape_steps)
+    assert np.abs(Us - Uo).max() < 1e-12
+    import scipy.sparse.linalg as sla
+    Vs = dims[0] * dims[1] * dims[2]
+    V = Vs * dims[3]
+    Vn = Vg.cpu().numpy()
+    d1 = (dims[0], dims[1], dims[2], 1)
+    for t in (0, 17):
+        Ut = np.ascontiguousarray(Uo[t * Vs:(t + 1) * Vs])
+
+        def mv(y, Ut=Ut):
+            return oracle.laplace(Ut, d1, y.reshape(Vs, 3)).reshape(-1)
+        op = sla.LinearOperator((3 * Vs, 3 * Vs), matvec=mv, dtype=np.complex128)
+        w = np.sort(sla.eigsh(op, k=pre.nv, which="SA", tol=1e-12, return_eigenvectors=False))
+        assert np.abs(w - lam[t]).max() < 1e-8
+        A = Vn[t].reshape(pre.nv, -1)
+        assert np.abs(np.conj(A) @ A.T - np.eye(pre.nv)).max() < 1e-11
