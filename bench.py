@@ -1,0 +1,204 @@
+"""Benchmark of the hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--no-cpu-baseline]
+
+Workload: the mixed-precision distillation set-up on a 16^3 x 32 lattice
+(synthetic links exp(i 0.25 sum r_a T_a), 5 APE steps alpha = 0.5 for the
+Laplacian, Wilson-clover kappa = 0.125, csw = 1.5, antiperiodic time, Nv = 32
+eigenvectors per timeslice, domains 4^3 x 8), solved to true relative residual
+1e-10 by BiCGStab with FP32-arithmetic inner solves inside FP64 defect
+correction.
+
+One step is one batch of the whole hot path: the four timeslices of one
+multi-site packing set (one timeslice per temporal layer of the 4^3 x 8
+partition) -- sources, full-operator solves (4 x 4 x 32 = 512 RHS), packed
+domain-restricted solves (128 solves carrying 512 logical RHS), perambulator
+projection, loops for five Gamma channels, and the full / factorised /
+subtracted correlators.  The value is logical RHS (full + restricted) per
+second over the timed steps; set-up (clover term, APE, eigenvectors) is timed
+once before and reported beside it.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "distillation RHS solved/s at rel. residual 1e-10; Dirac stencil HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+STENCIL_SOURCES = ["paper_2609_37049_amd/csrc/stencil.hip", "paper_2609_37049_amd/csrc/spinor_io.h"]
+
+
+def stencil_hash():
+    h = hashlib.sha256()
+    for p in STENCIL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_tag):
+    """HBM bytes per launch of the timed stencil, from committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration); null when
+    the kernel sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    ent = d.get(kernel_tag)
+    if not ent or ent.get("source_hash") != stencil_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(pre, seconds_budget=30.0):
+    """The oracle on the host cores: one full-operator CGNR solve of the same
+    workload to 1e-10 plus its projection at the source timeslice."""
+    import oracle
+    import synth
+    dims, bc = pre.dims, pre.bc
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    A = oracle.clover(U, dims, pre.kappa, pre.csw)
+    V = int(np.prod(dims))
+    Vs = V // dims[3]
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal((Vs, 3)) + 1j * rng.standard_normal((Vs, 3))
+    v /= np.linalg.norm(v)
+    b = np.zeros((V, 4, 3), dtype=np.complex128)
+    b[:Vs, 0, :] = v
+    t0 = time.perf_counter()
+    x, it, rr = oracle.cgnr(U, A, dims, bc, pre.kappa, b, tol=1e-10)
+    _ = np.einsum("xc,xbc->b", np.conj(v), x[:Vs])
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / dt, "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "sample": "1 full-operator RHS of the 16^3x32 workload: oracle FP64 CGNR to true rel. residual "
+                      "1e-10 (%d iterations, %.1f s) + its projection at the source timeslice; source = one "
+                      "normalised Gaussian colour vector on timeslice 0 in spin 0" % (it, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", choices=["bf16", "f32"], default="bf16")
+    ap.add_argument("--rhs-block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solves of different right-hand sides are independent, so "
+              "the path shards by right-hand side without exchange (see the design notes); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2609_37049_amd as d
+
+    pre = synth.PRESETS["prec_16x16x16x32"]
+    dims = pre.dims
+    T = dims[3]
+    codes = [d.G_1, d.G_5, d.G_X, d.G_Y, d.G_Z]
+    torch.cuda.set_device(0)
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    ctx = d.Context(dims, pre.bc, 0)
+    cut = synth.tiling_cuts(dims, pre.block)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.gauge_set(U)
+    ctx.clover_setup(pre.kappa, pre.csw)
+    ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
+    Vev, lam = ctx.laplace_eigvecs(pre.nv, 1e-11)
+    dom = ctx.domains(cut)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    inner = d.BF16 if args.inner == "bf16" else d.F32
+    P = ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block or 16)
+    nv = pre.nv
+    dev = "cuda:0"
+    tau_f = torch.zeros((T, nv, 4, nv, 4), dtype=torch.complex128, device=dev)
+    tau_b = torch.zeros_like(tau_f)
+    layer = pre.block[3]
+    groups = [sum(1 << (g + layer * k) for k in range(T // layer)) for g in range(layer)]
+    sign = torch.tensor([1.0, -1.0, -1.0, -1.0, -1.0], dtype=torch.float64, device=dev)[:, None]
+
+    def step(k):
+        msk = groups[k % len(groups)]
+        a1 = ctx.perambulators_tt(Vev, msk, P, tau_f)
+        n_full = ctx.last_solves()
+        a2 = ctx.perambulators_tt(Vev, msk, P, tau_b, dom)
+        n_blk = ctx.last_solves()
+        Lf = ctx.loops(tau_f, codes)
+        Lb = ctx.loops(tau_b, codes)
+        for g in range(len(codes)):
+            ctx.correlator(Lf[g:g + 1].contiguous(), (sign[g] * Lf[g:g + 1]).contiguous(),
+                           Lb[g:g + 1].contiguous(), (sign[g] * Lb[g:g + 1]).contiguous())
+        logical = 4 * nv * bin(msk).count("1") * 2
+        return logical, n_full, n_blk, max(a1.true_rel_residual, a2.true_rel_residual), a1, a2
+
+    for k in range(args.warmup):
+        step(k)
+        print("warmup step %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tag = {d.BF16: d.K_STENCIL_BF16, d.F32: d.K_STENCIL_F32}[inner]
+    ctx.profile_reset()
+    ctx.profile_stride(4)
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rhs = 0
+    solves = 0
+    worst = 0.0
+    iters = 0
+    for k in range(args.warmup, args.warmup + args.steps):
+        logical, nf, nb, res, a1, a2 = step(k)
+        rhs += logical
+        solves += nf + nb
+        worst = max(worst, res)
+        iters += a1.iters + a2.iters
+        print("timed step %d: %d logical RHS, %d solves, worst residual %.2e" % (k, logical, nf + nb, res),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    nl, ms, by = ctx.profile_get(tag)
+    avg_ms = ms / max(nl, 1)
+    achieved = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    kernel_tag = "k_dslash<%s>" % ("IOBF" if inner == d.BF16 else "IO32")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": load_traffic(kernel_tag),
+            "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, 16 RHS per launch)",
+            "avg_launch_ms": round(avg_ms, 5), "launches_timed": nl,
+            "alg_bytes_per_launch": round(by / max(nl, 1))}
+    out = {
+        "metric": METRIC, "value": round(rhs / dt, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16^3x32 Wilson-clover kappa=0.125 csw=1.5, Nv=32, domains 4^3x8, "
+                               "BiCGStab %s-storage/FP32 inner + FP64 defect correction to 1e-10" % args.inner,
+                   "lattice": "16x16x16x32", "nv": nv, "rhs_block": P.rhs_block, "inner_storage": args.inner,
+                   "outer": "f64", "logical_rhs_per_step": rhs // max(args.steps, 1),
+                   "solves_per_step": solves // max(args.steps, 1)},
+        "roofline": roof,
+        "worst_true_rel_residual": worst,
+        "inner_iterations": iters,
+        "setup_s": round(setup_s, 3),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pre)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

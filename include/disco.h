@@ -224,7 +224,15 @@ int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double*
 int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vev, int nv, const double* w,
                         const int* gammas, int ngamma, const disco_solver_params* p, void* L, void* tau_out,
                         disco_solver_stats* agg);
-/* Right-hand sides solved by the last disco_loops_distill call (packed count). */
+/* The perambulators tau(t,t) of disco_loops_distill alone, for the source
+ * timeslices whose bit is set in tmask (0 = all); tau_out (device,
+ * [T][nv][4][nv][4]) is written only at those t.  Lets a caller process a
+ * configuration in batches of timeslices (for D_Lambda, one batch per
+ * packing set) and form the loops afterwards with disco_loops. */
+int disco_perambulators_tt(disco_ctx* ctx, const disco_domains* dom, const void* Vev, int nv, unsigned long long tmask,
+                           const disco_solver_params* p, void* tau_out, disco_solver_stats* agg);
+/* Right-hand sides solved by the last disco_loops_distill or
+ * disco_perambulators_tt call (packed count). */
 long long disco_last_solves(const disco_ctx* ctx);
 /* Disconnected correlators (Methodology equations Cdisc, correlator_factorised,
  * subtracted_correlator, and corr1-corr4 of the Gaussian-profiled subsection),
@@ -247,9 +255,12 @@ int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, co
  * with HIP events recorded on the context's stream around each launch.
  * kernel: 0 = Wilson-clover stencil (any precision): bytes = algorithmic
  * bytes of those launches (each input/output spinor, the links and the clover
- * term counted once per site); 1 = FP64 matrix-core contraction (perambulator,
- * eigensolver Gram matrices): bytes holds the flop count instead. */
+ * term counted once per site); 10, 11, 12 = the same split by storage
+ * precision (FP64, FP32, BF16); 1 = FP64 matrix-core contraction
+ * (perambulator, eigensolver Gram matrices): bytes holds the flop count. */
 int disco_profile_enable(disco_ctx* ctx, int on);
+/* Time only every `stride`-th profiled launch of each family (default 1). */
+int disco_profile_stride(disco_ctx* ctx, int stride);
 int disco_profile_reset(disco_ctx* ctx);
 int disco_profile_get(disco_ctx* ctx, int kernel, long long* launches, double* total_ms, double* bytes);
 

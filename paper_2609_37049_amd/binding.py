@@ -21,6 +21,8 @@ HOST, DEVICE = 0, 1
 G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
 CGNR_F64, BICGSTAB_DC = 0, 1
 K_STENCIL = 0
+K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
+K_MFMA = 1
 
 
 class DiscoError(RuntimeError):
@@ -73,6 +75,9 @@ _SIGS.update({
     "disco_loops": ([P, P, I, I, P, P, I, P], I),
     "disco_loops_distill": ([P, P, P, I, P, P, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
     "disco_last_solves": ([P], LL),
+    "disco_perambulators_tt": ([P, P, P, I, ctypes.c_ulonglong, ctypes.POINTER(SolverParams), P,
+                                ctypes.POINTER(SolverStats)], I),
+    "disco_profile_stride": ([P, I], I),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
 })
 _OPTIONAL = {}
@@ -314,6 +319,12 @@ class Context:
                                             ctypes.byref(agg)))
         return L, tau, agg
 
+    def perambulators_tt(self, Vev, tmask, params: SolverParams, tau, dom: Domains | None = None):
+        agg = SolverStats()
+        self._chk(lib().disco_perambulators_tt(self.h, None if dom is None else dom.h, _dptr(Vev), Vev.shape[1],
+                                               int(tmask), ctypes.byref(params), _dptr(tau), ctypes.byref(agg)))
+        return agg
+
     def last_solves(self):
         return int(lib().disco_last_solves(self.h))
 
@@ -331,6 +342,9 @@ class Context:
     # -- profiling
     def profile_enable(self, on=True):
         self._chk(lib().disco_profile_enable(self.h, int(on)))
+
+    def profile_stride(self, stride):
+        self._chk(lib().disco_profile_stride(self.h, int(stride)))
 
     def profile_reset(self):
         self._chk(lib().disco_profile_reset(self.h))

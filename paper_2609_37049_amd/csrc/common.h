@@ -89,6 +89,11 @@ struct disco_ctx {
     bool have_clover = false;
     double kappa = 0, csw = 0;
 
+    // stencil traversal: trav[g] = {site, x | y<<8 | z<<16 | t<<24} in the order the
+    // stencil visits sites (each XCD takes one contiguous range of g)
+    int2* d_trav = nullptr;
+    int trav_kind = 0;
+
     // named, grow-only device workspaces
     std::map<std::string, std::pair<void*, size_t>> ws;
 
@@ -97,6 +102,8 @@ struct disco_ctx {
 
     // profiling
     bool prof_on = false;
+    int prof_stride = 1;
+    std::map<int, long long> prof_seen;  // launches seen per family (for the stride)
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
 };
@@ -143,7 +150,7 @@ void* ws_get(disco_ctx* ctx, const std::string& name, size_t bytes);
 void activate(disco_ctx* ctx);
 
 // launch helpers for profiling
-int prof_begin(disco_ctx* ctx);                // returns record index or -1
+int prof_begin(disco_ctx* ctx, int family);    // returns record index or -1 (not sampled)
 void prof_end(disco_ctx* ctx, int rec, int kernel, double bytes);
 
 // ----------------------------------------------------------------- launch geometry
@@ -233,6 +240,7 @@ struct StencilCall {
 int nq_of(int epi);
 int stencil_nsb(disco_ctx* ctx, int n);   // partial-sum slots per (rhs, quantity)
 int stencil_spb(int n);                    // sites per stencil block
+void build_traversal(disco_ctx* ctx);
 void stencil_launch(disco_ctx* ctx, const StencilCall& c);
 size_t native_bytes(const disco_ctx* ctx, int prec, int nrhs);
 void to_native(disco_ctx* ctx, int prec, int nrhs, const void* in, void* out);

@@ -42,8 +42,9 @@ static hipEvent_t ev_get(disco_ctx* ctx) {
     return e;
 }
 
-int prof_begin(disco_ctx* ctx) {
+int prof_begin(disco_ctx* ctx, int family) {
     if (!ctx->prof_on) return -1;
+    if ((ctx->prof_seen[family]++) % ctx->prof_stride) return -1;
     ProfRec r;
     r.a = ev_get(ctx);
     r.b = ev_get(ctx);
@@ -271,11 +272,14 @@ int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out
             ctx->bc[m] = bc[m];
             V *= dims[m];
         }
-        REQUIRE(V < (1L << 31), DISCO_EINVAL, "volume too large");
+        REQUIRE(V * 36 * 16 < (1L << 32), DISCO_EINVAL, "volume too large (links must stay below 4 GiB)");
         ctx->V = V;
         ctx->Vs = V / dims[3];
         ctx->device = device;
         activate(ctx);
+        REQUIRE(dims[0] <= 255 && dims[1] <= 255 && dims[2] <= 255 && dims[3] <= 255, DISCO_EINVAL,
+                "extents above 255 are not supported");
+        disco::build_traversal(ctx);
     });
     if (rc != DISCO_OK) {
         delete ctx;
@@ -295,6 +299,7 @@ int disco_destroy(disco_ctx* ctx) {
     hipFree(ctx->Usm);
     hipFree(ctx->A64);
     hipFree(ctx->A32);
+    hipFree(ctx->d_trav);
     for (auto& r : ctx->prof) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -436,6 +441,12 @@ int disco_profile_enable(disco_ctx* ctx, int on) {
     return DISCO_OK;
 }
 
+int disco_profile_stride(disco_ctx* ctx, int stride) {
+    if (!ctx || stride < 1) return DISCO_EINVAL;
+    ctx->prof_stride = stride;
+    return DISCO_OK;
+}
+
 int disco_profile_reset(disco_ctx* ctx) {
     if (!ctx) return DISCO_EINVAL;
     return guarded(ctx, [&] {
@@ -445,6 +456,7 @@ int disco_profile_reset(disco_ctx* ctx) {
             ctx->ev_pool.push_back(r.b);
         }
         ctx->prof.clear();
+        ctx->prof_seen.clear();
     });
 }
 
@@ -455,7 +467,8 @@ int disco_profile_get(disco_ctx* ctx, int kernel, long long* launches, double* t
         long long n = 0;
         double ms = 0, by = 0;
         for (auto& r : ctx->prof) {
-            if (r.kernel != kernel) continue;
+            const bool match = r.kernel == kernel || (kernel == 0 && r.kernel >= 10 && r.kernel <= 12);
+            if (!match) continue;
             float t = 0;
             HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
             ms += t;

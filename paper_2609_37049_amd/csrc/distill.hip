@@ -527,7 +527,7 @@ void zgemm_hn(disco_ctx* ctx, const double2* A, long lda, long sA, const double2
     int kchunk = ((K + nks - 1) / nks + 3) / 4 * 4;
     nks = (K + kchunk - 1) / kchunk;
     double2* P = (double2*)ws_get(ctx, "gemm_part", sizeof(double2) * (size_t)batch * nks * M * N);
-    int rec = prof_begin(ctx);
+    int rec = prof_begin(ctx, 1);
     hipLaunchKernelGGL(k_zgemm_hn, dim3((unsigned)(tiles * nks)), dim3(64), 0, ctx->stream, A, lda, sA, B, ldb, sB, P,
                        M, N, K, kchunk, nks, tilesM, tilesN);
     HIPCHK(hipGetLastError());
@@ -832,28 +832,29 @@ int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, co
     });
 }
 
-// End-to-end distillation loops: for every timeslice (or packed set of
-// timeslices for the domain-restricted operator) and every (i, alpha), build
-// the sources, solve, project at the source timeslices, and accumulate
-// tau(t,t); then form the loops.  Solutions are never all held: only one RHS
-// block at a time.
-int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vin, int nv, const double* w,
-                        const int* gammas, int ngamma, const disco_solver_params* P, void* L, void* tau_out,
-                        disco_solver_stats* agg) {
+// Perambulators tau(t,t) for the source timeslices in tmask (0 = all): for
+// every timeslice (or packed set of timeslices for the domain-restricted
+// operator) and every (i, alpha), build the sources, solve, project at the
+// source timeslices and store tau(t,t).  Solutions are never all held: only
+// one RHS block at a time.
+int disco_perambulators_tt(disco_ctx* ctx, const disco_domains* dom, const void* Vin, int nv, unsigned long long tmask,
+                           const disco_solver_params* P, void* tau_out, disco_solver_stats* agg) {
     if (!ctx) return DISCO_EINVAL;
     bool all_ok = true;
     int rc = guarded(ctx, [&] {
-        REQUIRE(Vin && gammas && P && L && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
-        REQUIRE(ctx->have_clover, DISCO_ESTATE, "loops before clover_setup");
+        REQUIRE(Vin && P && tau_out && nv > 0, DISCO_EINVAL, "bad argument");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "perambulators before clover_setup");
         REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
         const int T = ctx->dims[3];
         REQUIRE(T <= 64, DISCO_EINVAL, "at most 64 timeslices");
+        const unsigned long long all = T == 64 ? ~0ULL : ((1ULL << T) - 1);
+        if (tmask == 0) tmask = all;
+        REQUIRE((tmask & ~all) == 0, DISCO_EINVAL, "tmask names timeslices beyond T");
         activate(ctx);
         const long V = ctx->V, Vs = ctx->Vs, K = 3 * Vs;
         double2* Vi = (double2*)ws_get(ctx, "ld_V", sizeof(double2) * T * K * nv);
         k_eig_import<<<grid_for((long)T * nv * K), 256, 0, ctx->stream>>>((const double2*)Vin, Vi, T, K, nv);
-        double2* tau = tau_out ? (double2*)tau_out
-                               : (double2*)ws_get(ctx, "ld_tau", sizeof(double2) * (size_t)T * nv * 4 * nv * 4);
+        double2* tau = (double2*)tau_out;
         // packing sets: one timeslice per temporal layer of the partition
         std::vector<unsigned long long> sets;
         if (dom) {
@@ -869,7 +870,7 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
                 std::vector<int> curl;
                 for (int k = 1; k <= T; k++) {
                     const int t = (anchor + k) % T;
-                    curl.push_back(t);
+                    if ((tmask >> t) & 1ULL) curl.push_back(t);
                     if (dom->cut[3 * lm + t]) {
                         layers.push_back(curl);
                         curl.clear();
@@ -877,7 +878,7 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
                 }
                 size_t maxlen = 0;
                 for (auto& l : layers) maxlen = std::max(maxlen, l.size());
-                // set p holds the p-th timeslice of every layer long enough
+                // set p holds the p-th requested timeslice of every layer long enough
                 for (size_t p = 0; p < maxlen; p++) {
                     unsigned long long msk = 0;
                     for (auto& l : layers)
@@ -899,7 +900,9 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
         long long solves = 0, iters = 0;
         double worst = 0;
         int fb = 0, outer = 0;
-        for (unsigned long long msk : sets) {
+        for (unsigned long long msk0 : sets) {
+            const unsigned long long msk = msk0 & tmask;
+            if (!msk) continue;
             for (int r0 = 0; r0 < nrhs_set; r0 += blk) {
                 const int n = std::min(blk, nrhs_set - r0);
                 std::vector<SrcSpec> spec(n);
@@ -926,11 +929,6 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
                 HIPCHK(hipStreamSynchronize(ctx->stream));  // spec buffer is reused by the next block
             }
         }
-        int* gd = (int*)ws_get(ctx, "lp_g", sizeof(int) * ngamma);
-        HIPCHK(hipMemcpyAsync(gd, gammas, sizeof(int) * ngamma, hipMemcpyHostToDevice, ctx->stream));
-        k_loops<<<ngamma * T, 64, 0, ctx->stream>>>(tau, T, nv, w, gd, ngamma, (double2*)L);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(ctx->stream));
         if (agg) {
             agg->iters = (int)std::min<long long>(iters, 2147483647LL);
             agg->outer_iters = outer;
@@ -938,7 +936,6 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
             agg->converged = all_ok;
             agg->true_rel_residual = worst;
         }
-        if (agg) agg->iters = (int)std::min<long long>(iters, 2147483647LL);
         ctx->last_solves = solves;
     });
     if (rc == DISCO_OK && !all_ok) {
@@ -946,6 +943,28 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
         return DISCO_ENOCONV;
     }
     return rc;
+}
+
+// End-to-end loops: all perambulators tau(t,t), then the loops.
+int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vin, int nv, const double* w,
+                        const int* gammas, int ngamma, const disco_solver_params* P, void* L, void* tau_out,
+                        disco_solver_stats* agg) {
+    if (!ctx) return DISCO_EINVAL;
+    void* tau = tau_out;
+    int rc = guarded(ctx, [&] {
+        REQUIRE(Vin && gammas && P && L && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
+        if (!tau) tau = ws_get(ctx, "ld_tau", sizeof(double2) * (size_t)ctx->dims[3] * nv * 4 * nv * 4);
+    });
+    if (rc != DISCO_OK) return rc;
+    int rs = disco_perambulators_tt(ctx, dom, Vin, nv, 0, P, tau, agg);
+    if (rs != DISCO_OK && rs != DISCO_ENOCONV) return rs;
+    long long solves = ctx->last_solves;
+    std::string err = ctx->err;
+    int rl = disco_loops(ctx, tau, ctx->dims[3], nv, w, gammas, ngamma, L);
+    ctx->last_solves = solves;
+    if (rl != DISCO_OK) return rl;
+    if (rs == DISCO_ENOCONV) ctx->err = err;
+    return rs;
 }
 
 }  // extern "C"

@@ -31,6 +31,46 @@ __device__ __forceinline__ float d2f_odd(double d) {
     return f;
 }
 
+// Element at byte offset `off` (32-bit, per lane) past the wave-uniform base
+// b + plane_bytes: lets the compiler address every plane with one scalar base
+// and the same vector offset instead of a 64-bit address per load.  All
+// blocks handed to the stencil are below 4 GiB per plane.
+template <typename E>
+__device__ __forceinline__ E ld_at(const void* b, size_t plane_bytes, unsigned off) {
+    const char* base = (const char*)b + plane_bytes;
+    return *(const E*)(base + off);
+}
+template <typename E>
+__device__ __forceinline__ void st_at(void* b, size_t plane_bytes, unsigned off, E v) {
+    char* base = (char*)b + plane_bytes;
+    *(E*)(base + off) = v;
+}
+
+// Buffer-resource loads: one descriptor (wave-uniform, scalar registers) for a
+// whole array, a 32-bit per-lane byte offset and a scalar per-plane offset.
+// The hardware checks every access against num_records and returns zero
+// beyond it.  Arrays passed this way stay below 4 GiB.
+typedef __amdgpu_buffer_rsrc_t brsrc;
+__device__ __forceinline__ brsrc make_rsrc(const void* p, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u4v bld16(brsrc r, unsigned voff, unsigned soff) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+__device__ __forceinline__ u2v bld8(brsrc r, unsigned voff, unsigned soff) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+}
+
+// Read-only views handed to the stencil: base pointer, bytes, and whether the
+// buffer path applies (nbytes < 4 GiB).
+struct RoView {
+    const void* p;
+    unsigned nbytes;
+    int buf;
+};
+
 struct IO64 {
     typedef double T;
     typedef double2 LinkT;
@@ -38,34 +78,53 @@ struct IO64 {
     static constexpr int planes = 12;
     static constexpr int spinor_bytes = 192;
     static constexpr int real_bytes_link = 8;
-    __device__ __forceinline__ static void load(const void* b, long V, int n, long r, long s, cx<T> p[12]) {
-        const double2* q = (const double2*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void load(const void* b, long V, int n, int r, int s, cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 v = q[k * ps];
+            double2 v = ld_at<double2>(b, k * ps, off);
             p[k] = mk(v.x, v.y);
         }
     }
-    __device__ __forceinline__ static void store(void* b, long V, int n, long r, long s, const cx<T> p[12]) {
-        double2* q = (double2*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
-        for (int k = 0; k < 12; k++) q[k * ps] = make_double2(p[k].re, p[k].im);
+        for (int k = 0; k < 12; k++) st_at(b, k * ps, off, make_double2(p[k].re, p[k].im));
     }
-    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, long s, cx<T> u[9]) {
+    template <bool BUF>
+    __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
+        if constexpr (BUF) {
+            const brsrc rs = make_rsrc(b.p, b.nbytes);
+            const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+            const unsigned ps = (unsigned)V * (unsigned)n * 16u;
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            double2 v = U[((long)mu * 9 + k) * V + s];
-            u[k] = mk(v.x, v.y);
+            for (int k = 0; k < 12; k++) {
+                u4v v = bld16(rs, off, k * ps);
+                p[k] = mk(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2]));
+            }
+        } else {
+            load(b.p, V, n, r, s, p);
         }
     }
-    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, long s, T f[36]) {
+    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, int s, cx<T> u[9]) {
+        const brsrc rs = make_rsrc(U, (unsigned)(V * 36 * 16));
+        const unsigned off = (unsigned)s * 16u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            u4v v = bld16(rs, off, (unsigned)((mu * 9 + k) * V * 16));
+            u[k] = mk(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2]));
+        }
+    }
+    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, int s, T f[36]) {
+        const brsrc rs = make_rsrc(A, (unsigned)(V * 36 * 16));
+        const unsigned off = (unsigned)s * 16u;
 #pragma unroll
         for (int q = 0; q < 18; q++) {
-            double2 v = A[((long)blk * 18 + q) * V + s];
-            f[2 * q] = v.x;
-            f[2 * q + 1] = v.y;
+            u4v v = bld16(rs, off, (unsigned)((blk * 18 + q) * V * 16));
+            f[2 * q] = __hiloint2double(v[1], v[0]);
+            f[2 * q + 1] = __hiloint2double(v[3], v[2]);
         }
     }
 };
@@ -77,37 +136,58 @@ struct IO32 {
     static constexpr int planes = 6;
     static constexpr int spinor_bytes = 96;
     static constexpr int real_bytes_link = 4;
-    __device__ __forceinline__ static void load(const void* b, long V, int n, long r, long s, cx<T> p[12]) {
-        const float4* q = (const float4*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void load(const void* b, long V, int n, int r, int s, cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            float4 v = q[k * ps];
+            float4 v = ld_at<float4>(b, k * ps, off);
             p[2 * k] = mk(v.x, v.y);
             p[2 * k + 1] = mk(v.z, v.w);
         }
     }
-    __device__ __forceinline__ static void store(void* b, long V, int n, long r, long s, const cx<T> p[12]) {
-        float4* q = (float4*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
-        for (int k = 0; k < 6; k++) q[k * ps] = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
+        for (int k = 0; k < 6; k++)
+            st_at(b, k * ps, off, make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im));
     }
-    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, long s, cx<T> u[9]) {
+    template <bool BUF>
+    __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
+        if constexpr (BUF) {
+            const brsrc rs = make_rsrc(b.p, b.nbytes);
+            const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+            const unsigned ps = (unsigned)V * (unsigned)n * 16u;
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            float2 v = U[((long)mu * 9 + k) * V + s];
-            u[k] = mk(v.x, v.y);
+            for (int k = 0; k < 6; k++) {
+                u4v v = bld16(rs, off, k * ps);
+                p[2 * k] = mk(__uint_as_float(v[0]), __uint_as_float(v[1]));
+                p[2 * k + 1] = mk(__uint_as_float(v[2]), __uint_as_float(v[3]));
+            }
+        } else {
+            load(b.p, V, n, r, s, p);
         }
     }
-    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, long s, T f[36]) {
+    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, int s, cx<T> u[9]) {
+        const brsrc rs = make_rsrc(U, (unsigned)(V * 36 * 8));
+        const unsigned off = (unsigned)s * 8u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            u2v v = bld8(rs, off, (unsigned)((mu * 9 + k) * V * 8));
+            u[k] = mk(__uint_as_float(v[0]), __uint_as_float(v[1]));
+        }
+    }
+    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, int s, T f[36]) {
+        const brsrc rs = make_rsrc(A, (unsigned)(V * 18 * 16));
+        const unsigned off = (unsigned)s * 16u;
 #pragma unroll
         for (int q = 0; q < 9; q++) {
-            float4 v = A[((long)blk * 9 + q) * V + s];
-            f[4 * q] = v.x;
-            f[4 * q + 1] = v.y;
-            f[4 * q + 2] = v.z;
-            f[4 * q + 3] = v.w;
+            u4v v = bld16(rs, off, (unsigned)((blk * 9 + q) * V * 16));
+            f[4 * q] = __uint_as_float(v[0]);
+            f[4 * q + 1] = __uint_as_float(v[1]);
+            f[4 * q + 2] = __uint_as_float(v[2]);
+            f[4 * q + 3] = __uint_as_float(v[3]);
         }
     }
 };
@@ -119,30 +199,55 @@ struct IOBF {
     static constexpr int planes = 3;
     static constexpr int spinor_bytes = 48;
     static constexpr int real_bytes_link = 4;
-    __device__ __forceinline__ static void load(const void* b, long V, int n, long r, long s, cx<T> p[12]) {
-        const uint4* q = (const uint4*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void load(const void* b, long V, int n, int r, int s, cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            uint4 v = q[k * ps];
+            uint4 v = ld_at<uint4>(b, k * ps, off);
             p[4 * k + 0] = mk(bf2f(v.x & 0xffffu), bf2f(v.x >> 16));
             p[4 * k + 1] = mk(bf2f(v.y & 0xffffu), bf2f(v.y >> 16));
             p[4 * k + 2] = mk(bf2f(v.z & 0xffffu), bf2f(v.z >> 16));
             p[4 * k + 3] = mk(bf2f(v.w & 0xffffu), bf2f(v.w >> 16));
         }
     }
-    __device__ __forceinline__ static uint32_t pack(cx<T> c) { return f2bf_rne(c.re) | (f2bf_rne(c.im) << 16); }
-    __device__ __forceinline__ static void store(void* b, long V, int n, long r, long s, const cx<T> p[12]) {
-        uint4* q = (uint4*)b + s * n + r;
-        const long ps = V * n;
+    __device__ __forceinline__ static void unpack(uint32_t w, cx<T>& c) { c = mk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)); }
+    template <bool BUF>
+    __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
+        if constexpr (BUF) {
+            const brsrc rs = make_rsrc(b.p, b.nbytes);
+            const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+            const unsigned ps = (unsigned)V * (unsigned)n * 16u;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                u4v v = bld16(rs, off, k * ps);
+                unpack(v[0], p[4 * k + 0]);
+                unpack(v[1], p[4 * k + 1]);
+                unpack(v[2], p[4 * k + 2]);
+                unpack(v[3], p[4 * k + 3]);
+            }
+        } else {
+            load(b.p, V, n, r, s, p);
+        }
+    }
+    // (re, im) -> two bf16 in one word, round to nearest even (one v_cvt_pk_bf16_f32)
+    __device__ __forceinline__ static uint32_t pack(cx<T> c) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+        f2v f = {c.re, c.im};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, b2v));
+    }
+    __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
+        const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
+        const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 3; k++)
-            q[k * ps] = make_uint4(pack(p[4 * k]), pack(p[4 * k + 1]), pack(p[4 * k + 2]), pack(p[4 * k + 3]));
+            st_at(b, k * ps, off, make_uint4(pack(p[4 * k]), pack(p[4 * k + 1]), pack(p[4 * k + 2]), pack(p[4 * k + 3])));
     }
-    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, long s, cx<T> u[9]) {
+    __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, int s, cx<T> u[9]) {
         IO32::load_link(U, V, mu, s, u);
     }
-    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, long s, T f[36]) {
+    __device__ __forceinline__ static void load_clover(const CloverT* A, long V, int blk, int s, T f[36]) {
         IO32::load_clover(A, V, blk, s, f);
     }
 };

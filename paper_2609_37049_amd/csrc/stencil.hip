@@ -12,6 +12,9 @@
 // inside each domain).  The optional epilogue fuses the Krylov reductions
 // (deterministic per-block partial sums in FP64).
 #include <algorithm>
+#include <cstdlib>
+#include <string>
+#include <vector>
 
 #include "spinor_io.h"
 
@@ -20,13 +23,14 @@ namespace {
 constexpr int kStencilBlock = kMaxBlock;
 
 struct StencilArgs {
-    const void* in;
+    RoView in;
     void* out;
-    const void* aux;   // b of out = b - D in
-    const void* aux2;  // w of <w, out>
+    RoView aux;   // b of out = b - D in
+    RoView aux2;  // w of <w, out>
     const void* U;
     const void* A;
     const uint8_t* mask;
+    const int2* trav;
     double2* part;
     long V;
     int L[4];
@@ -85,13 +89,35 @@ __device__ __forceinline__ void expand(cx<T> acc[12], const cx<T> u[6]) {
     }
 }
 
+// acc += a * b and acc += conj(a) * b as explicit fused multiply-add chains
+// (four FMAs per complex product; the compiler may not reassociate)
+template <typename T>
+__device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+template <typename T>
+__device__ __forceinline__ void cjmac(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+
 template <typename T>
 __device__ __forceinline__ void su3_mul(const cx<T> u[9], const cx<T> h[6], cx<T> o[6]) {
 #pragma unroll
     for (int sp = 0; sp < 2; sp++)
 #pragma unroll
-        for (int a = 0; a < 3; a++)
-            o[sp * 3 + a] = u[a * 3 + 0] * h[sp * 3 + 0] + u[a * 3 + 1] * h[sp * 3 + 1] + u[a * 3 + 2] * h[sp * 3 + 2];
+        for (int a = 0; a < 3; a++) {
+            cx<T> acc = mk((T)0, (T)0);
+            cmac(acc, u[a * 3 + 0], h[sp * 3 + 0]);
+            cmac(acc, u[a * 3 + 1], h[sp * 3 + 1]);
+            cmac(acc, u[a * 3 + 2], h[sp * 3 + 2]);
+            o[sp * 3 + a] = acc;
+        }
 }
 
 template <typename T>
@@ -99,9 +125,13 @@ __device__ __forceinline__ void su3_dag_mul(const cx<T> u[9], const cx<T> h[6], 
 #pragma unroll
     for (int sp = 0; sp < 2; sp++)
 #pragma unroll
-        for (int a = 0; a < 3; a++)
-            o[sp * 3 + a] =
-                cjmul(u[0 * 3 + a], h[sp * 3 + 0]) + cjmul(u[1 * 3 + a], h[sp * 3 + 1]) + cjmul(u[2 * 3 + a], h[sp * 3 + 2]);
+        for (int a = 0; a < 3; a++) {
+            cx<T> acc = mk((T)0, (T)0);
+            cjmac(acc, u[0 * 3 + a], h[sp * 3 + 0]);
+            cjmac(acc, u[1 * 3 + a], h[sp * 3 + 1]);
+            cjmac(acc, u[2 * 3 + a], h[sp * 3 + 2]);
+            o[sp * 3 + a] = acc;
+        }
 }
 
 template <typename T>
@@ -119,28 +149,33 @@ __device__ __forceinline__ void clover6(const T f[36], const cx<T>* x, cx<T>* y)
     for (int i = 0; i < 6; i++)
 #pragma unroll
         for (int j = i + 1; j < 6; j++, m++) {
-            cx<T> a = mk(f[6 + 2 * m], f[7 + 2 * m]);
-            y[i] = y[i] + a * x[j];
-            y[j] = y[j] + cjmul(a, x[i]);
+            const cx<T> a = mk(f[6 + 2 * m], f[7 + 2 * m]);
+            cmac(y[i], a, x[j]);
+            cjmac(y[j], a, x[i]);
         }
 }
 
 // both hops in direction MU for right-hand side r at site s
-template <class IO, int MU>
-__device__ __forceinline__ void hops(const StencilArgs& a, long s, const int* x, uint32_t m, int n, long r,
-                                     cx<typename IO::T> acc[12]) {
+template <class IO, bool BUF, bool STAGE, int MU>
+__device__ __forceinline__ void hops(const StencilArgs& a, int s, const int* x, uint32_t m, int n, int r,
+                                     const float2* sl, cx<typename IO::T> acc[12]) {
     typedef typename IO::T T;
     const typename IO::LinkT* U = (const typename IO::LinkT*)a.U;
     const long V = a.V;
     const int L = a.L[MU];
-    const long st = a.st[MU];
+    const int st = (int)a.st[MU];
     if (m & (1u << (2 * MU))) {
         // forward: (1 - gamma_mu) U_mu(x) psi(x+mu), boundary phase at the wrap
         const bool wrap = x[MU] == L - 1;
-        const long nb = wrap ? s - (long)(L - 1) * st : s + st;
+        const int nb = wrap ? s - (L - 1) * st : s + st;
         cx<T> u[9], p[12], h[6], o[6];
-        IO::load(a.in, V, n, r, nb, p);
-        IO::load_link(U, V, MU, s, u);
+        IO::template loadv<BUF>(a.in, V, n, r, nb, p);
+        if constexpr (STAGE) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = mk((T)sl[(2 * MU) * 9 + k].x, (T)sl[(2 * MU) * 9 + k].y);
+        } else {
+            IO::load_link(U, V, MU, s, u);
+        }
         if (a.dagger) g5(p);
         project<MU, true>(p, h);
         if (wrap) {
@@ -154,10 +189,15 @@ __device__ __forceinline__ void hops(const StencilArgs& a, long s, const int* x,
     if (m & (2u << (2 * MU))) {
         // backward: (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
         const bool wrap = x[MU] == 0;
-        const long nb = wrap ? s + (long)(L - 1) * st : s - st;
+        const int nb = wrap ? s + (L - 1) * st : s - st;
         cx<T> u[9], p[12], h[6], o[6];
-        IO::load(a.in, V, n, r, nb, p);
-        IO::load_link(U, V, MU, nb, u);
+        IO::template loadv<BUF>(a.in, V, n, r, nb, p);
+        if constexpr (STAGE) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = mk((T)sl[(2 * MU + 1) * 9 + k].x, (T)sl[(2 * MU + 1) * 9 + k].y);
+        } else {
+            IO::load_link(U, V, MU, nb, u);
+        }
         if (a.dagger) g5(p);
         project<MU, false>(p, h);
         if (wrap) {
@@ -176,7 +216,16 @@ struct EpiCount {
                               ((EPI & disco::EPI_DOTIN) ? 1 : 0);
 };
 
-template <class IO, int EPI>
+// With STAGE (FP32 links and clover, at most kStageSites sites per block) the
+// block first copies the eight links of each of its sites (U_mu(x) and
+// U_mu(x-mu)) and their clover blocks into LDS with all lanes cooperating;
+// the n lanes of a site then read them from LDS instead of each issuing the
+// same global loads.
+constexpr int kStageSites = 32;
+constexpr int kStageLinkBytes = 8 * 9 * 8;   // 8 links x 9 complex float
+constexpr int kStageCloverBytes = 18 * 16;   // 2 blocks x 9 float4
+
+template <class IO, int EPI, bool BUF, bool STAGE>
 __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
     typedef typename IO::T T;
     constexpr int NQ = EpiCount<EPI>::nq;
@@ -186,34 +235,65 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
     if (sb < 0) return;
     const int t = threadIdx.x;
     const int nact = spb * n;
-    const long s = (long)sb * spb + t / n;
-    const long r = t % n;
+    const int g = sb * spb + t / n;
+    const int r = t % n;
     const long V = a.V;
     double red[NQ > 0 ? 2 * NQ : 1];
 #pragma unroll
     for (int k = 0; k < (NQ > 0 ? 2 * NQ : 1); k++) red[k] = 0;
-
-    if (t < nact && s < V) {
-        int x[4];
-        {
-            long q = s;
-            x[0] = (int)(q % a.L[0]); q /= a.L[0];
-            x[1] = (int)(q % a.L[1]); q /= a.L[1];
-            x[2] = (int)(q % a.L[2]); q /= a.L[2];
-            x[3] = (int)q;
+    extern __shared__ __align__(16) unsigned char stage_mem[];
+    const float2* sl = nullptr;
+    const float4* sa = nullptr;
+    if constexpr (STAGE) {
+        float2* sU = (float2*)stage_mem;
+        float4* sA = (float4*)(stage_mem + spb * kStageLinkBytes);
+        const float2* U = (const float2*)a.U;
+        const float4* A = (const float4*)a.A;
+        const int g0 = sb * spb;
+        for (int e = t; e < spb * 72; e += kStencilBlock) {
+            const int i = e / 72, rem = e - i * 72, d = rem / 9, k = rem - d * 9;
+            const int gi = g0 + i;
+            float2 v = make_float2(0.f, 0.f);
+            if (gi < V) {
+                const int2 tr = a.trav[gi];
+                const int mu = d >> 1;
+                int site = tr.x;
+                if (d & 1) {
+                    const int xm = (tr.y >> (8 * mu)) & 0xff;
+                    site = xm == 0 ? site + (a.L[mu] - 1) * (int)a.st[mu] : site - (int)a.st[mu];
+                }
+                v = U[((long)mu * 9 + k) * V + site];
+            }
+            sU[i * 72 + d * 9 + k] = v;
         }
+        for (int e = t; e < spb * 18; e += kStencilBlock) {
+            const int i = e / 18, q = e - i * 18;
+            const int gi = g0 + i;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gi < V) v = A[((long)(q / 9) * 9 + (q % 9)) * V + a.trav[gi].x];
+            sA[i * 18 + q] = v;
+        }
+        __syncthreads();
+        sl = sU + (t / n) * 72;
+        sa = sA + (t / n) * 18;
+    }
+
+    if (t < nact && g < V) {
+        const int2 tr = a.trav[g];
+        const int s = tr.x;
+        const int x[4] = {tr.y & 0xff, (tr.y >> 8) & 0xff, (tr.y >> 16) & 0xff, (tr.y >> 24) & 0xff};
         const uint32_t m = a.mask ? (uint32_t)a.mask[s] : 0xffu;
         cx<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = mk((T)0, (T)0);
-        hops<IO, 0>(a, s, x, m, n, r, acc);
-        hops<IO, 1>(a, s, x, m, n, r, acc);
-        hops<IO, 2>(a, s, x, m, n, r, acc);
-        hops<IO, 3>(a, s, x, m, n, r, acc);
+        hops<IO, BUF, STAGE, 0>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, 1>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, 2>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, 3>(a, s, x, m, n, r, sl, acc);
 
         // site-local part: A(x) psi(x) - kappa * hops
         cx<T> p[12], o[12];
-        IO::load(a.in, V, n, r, s, p);
+        IO::template loadv<BUF>(a.in, V, n, r, s, p);
         cx<T> pin[12];
         if (EPI & disco::EPI_DOTIN) {
 #pragma unroll
@@ -222,18 +302,33 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         if (a.dagger) g5(p);
         {
             T f[36];
-            IO::load_clover((const typename IO::CloverT*)a.A, V, 0, s, f);
-            clover6(f, p, o);
-            IO::load_clover((const typename IO::CloverT*)a.A, V, 1, s, f);
-            clover6(f, p + 6, o + 6);
+            if constexpr (STAGE) {
+#pragma unroll
+                for (int b = 0; b < 2; b++) {
+#pragma unroll
+                    for (int q = 0; q < 9; q++) {
+                        const float4 v = sa[b * 9 + q];
+                        f[4 * q] = v.x;
+                        f[4 * q + 1] = v.y;
+                        f[4 * q + 2] = v.z;
+                        f[4 * q + 3] = v.w;
+                    }
+                    clover6(f, p + 6 * b, o + 6 * b);
+                }
+            } else {
+                IO::load_clover((const typename IO::CloverT*)a.A, V, 0, s, f);
+                clover6(f, p, o);
+                IO::load_clover((const typename IO::CloverT*)a.A, V, 1, s, f);
+                clover6(f, p + 6, o + 6);
+            }
         }
         const T kap = (T)a.kappa;
 #pragma unroll
-        for (int k = 0; k < 12; k++) o[k] = o[k] - kap * acc[k];
+        for (int k = 0; k < 12; k++) o[k] = mk(fma(-kap, acc[k].re, o[k].re), fma(-kap, acc[k].im, o[k].im));
         if (a.dagger) g5(o);
         if (EPI & disco::EPI_RESID) {
             cx<T> b[12];
-            IO::load(a.aux, V, n, r, s, b);
+            IO::template loadv<BUF>(a.aux, V, n, r, s, b);
 #pragma unroll
             for (int k = 0; k < 12; k++) o[k] = b[k] - o[k];
         }
@@ -241,7 +336,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         int q = 0;
         if (EPI & disco::EPI_DOTAUX) {
             cx<T> w[12];
-            IO::load(a.aux2, V, n, r, s, w);
+            IO::template loadv<BUF>(a.aux2, V, n, r, s, w);
             double re = 0, im = 0;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
@@ -311,7 +406,20 @@ __global__ void k_from_native(const void* __restrict__ in, double2* __restrict__
 
 template <class IO, int EPI>
 void launch_one(disco_ctx* ctx, const StencilArgs& a) {
-    hipLaunchKernelGGL((k_dslash<IO, EPI>), dim3(xcd_grid(a.nsb)), dim3(kStencilBlock), 0, ctx->stream, a);
+    const dim3 grid(xcd_grid(a.nsb)), block(kStencilBlock);
+    const bool stage = sizeof(typename IO::T) == 4 && a.spb <= kStageSites && !getenv("DISCO_NO_STAGE");
+    if (stage) {
+        const size_t shm = (size_t)a.spb * (kStageLinkBytes + kStageCloverBytes);
+        if (a.in.buf)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true>), grid, block, shm, ctx->stream, a);
+        else
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, true>), grid, block, shm, ctx->stream, a);
+    } else {
+        if (a.in.buf)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false>), grid, block, 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, false>), grid, block, 0, ctx->stream, a);
+    }
 }
 
 template <class IO>
@@ -338,6 +446,47 @@ int nq_of(int epi) {
 
 int stencil_spb(int n) { return n >= kStencilBlock ? 1 : kStencilBlock / n; }
 
+// Site order of the stencil.  Each XCD (8 contiguous ranges of the order)
+// takes one slab of Lt/8 timeslices when Lt is a multiple of 8.  Inside a slab
+// the order is x fastest, then y within a tile of yt rows, then t within the
+// slab, then z, then the y tiles: hops in t and z then land a few hundred
+// sites away in the visiting order (instead of a whole timeslice), so the
+// neighbours of the sites in flight are still in that XCD's L2.  DISCO_TRAVERSAL
+// = natural restores lexicographic order.
+void build_traversal(disco_ctx* ctx) {
+    const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2], Lt = ctx->dims[3];
+    const long V = ctx->V;
+    std::vector<int2> tr(V);
+    const char* env = getenv("DISCO_TRAVERSAL");
+    const bool natural = env && std::string(env) == "natural";
+    auto put = [&](long g, int x, int y, int z, int t) {
+        tr[g].x = (int)(x + (long)Lx * (y + (long)Ly * (z + (long)Lz * t)));
+        tr[g].y = x | (y << 8) | (z << 16) | (t << 24);
+    };
+    long g = 0;
+    if (natural) {
+        for (int t = 0; t < Lt; t++)
+            for (int z = 0; z < Lz; z++)
+                for (int y = 0; y < Ly; y++)
+                    for (int x = 0; x < Lx; x++) put(g++, x, y, z, t);
+    } else {
+        const int nch = (Lt % 8 == 0) ? 8 : 1;
+        const int tc = Lt / nch;
+        int yt = 1;
+        for (int c = 1; c <= Ly; c++)
+            if (Ly % c == 0 && (long)Lx * c * tc <= 320) yt = c;
+        for (int ch = 0; ch < nch; ch++)
+            for (int yb = 0; yb < Ly / yt; yb++)
+                for (int z = 0; z < Lz; z++)
+                    for (int tl = 0; tl < tc; tl++)
+                        for (int yi = 0; yi < yt; yi++)
+                            for (int x = 0; x < Lx; x++) put(g++, x, yb * yt + yi, z, ch * tc + tl);
+    }
+    ctx->trav_kind = natural ? 0 : 1;
+    HIPCHK(hipMalloc(&ctx->d_trav, sizeof(int2) * V));
+    HIPCHK(hipMemcpy(ctx->d_trav, tr.data(), sizeof(int2) * V, hipMemcpyHostToDevice));
+}
+
 int stencil_nsb(disco_ctx* ctx, int n) {
     int spb = stencil_spb(n);
     return (int)((ctx->V + spb - 1) / spb);
@@ -348,11 +497,14 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     REQUIRE(c.nrhs >= 1 && c.nrhs <= kStencilBlock, DISCO_EINVAL, "nrhs per launch must be in 1..%d", kStencilBlock);
     REQUIRE(!(c.dagger && (c.epi & EPI_DOTIN)), DISCO_EINVAL, "DOTIN epilogue with dagger");
     StencilArgs a;
-    a.in = c.in;
+    const size_t blk = native_bytes(ctx, c.prec, c.nrhs);
+    const int buf = blk < (1ULL << 32) ? 1 : 0;
+    a.in = RoView{c.in, (unsigned)blk, buf};
     a.out = c.out;
-    a.aux = c.aux;
-    a.aux2 = c.aux2;
+    a.aux = RoView{c.aux, (unsigned)blk, buf};
+    a.aux2 = RoView{c.aux2, (unsigned)blk, buf};
     a.mask = c.mask;
+    a.trav = ctx->d_trav;
     a.part = c.part;
     a.V = ctx->V;
     long st = 1;
@@ -371,7 +523,7 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     double sg = c.prec == DISCO_F64 ? 8 : 4;                             // bytes per link/clover real
     int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & EPI_DOTAUX) ? 1 : 0);
     double bytes = (double)ctx->V * (c.nrhs * nvec * 24 * sp + 72 * sg + 72 * sg + (c.mask ? 1 : 0));
-    int rec = prof_begin(ctx);
+    int rec = prof_begin(ctx, 10 + c.prec);
     if (c.prec == DISCO_F64) {
         a.U = ctx->U64;
         a.A = ctx->A64;
@@ -388,7 +540,7 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
         disco_throw(DISCO_EINVAL, "bad precision %d", c.prec);
     }
     HIPCHK(hipGetLastError());
-    prof_end(ctx, rec, 0, bytes);
+    prof_end(ctx, rec, 10 + c.prec, bytes);
 }
 
 size_t native_bytes(const disco_ctx* ctx, int prec, int nrhs) {
