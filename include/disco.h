@@ -143,6 +143,16 @@ int disco_from_native(disco_ctx* ctx, int prec, int nrhs, const void* in_native,
 int disco_dirac_apply_native(disco_ctx* ctx, const disco_domains* dom, int prec, int dagger, int nrhs,
                              const void* in_native, void* out_native);
 
+/* ---------------------------------------------------------------- options */
+enum {
+    DISCO_OPT_GRAPHS = 1, /* 1 (default): inner Krylov iterations run as captured HIP graphs
+                           * (captured on a private stream, launched on the context stream;
+                           * skipped while profiling is enabled); 0: eager launches */
+    DISCO_OPT_STAGE = 2   /* LDS staging of links/clover in FP32/BF16 stencils: -1 auto
+                           * (16 or more right-hand sides per launch), 0 off, 1 on */
+};
+int disco_set_option(disco_ctx* ctx, int option, int value);
+
 /* ---------------------------------------------------------------- solver */
 typedef struct {
     int method;        /* DISCO_CGNR_F64 or DISCO_BICGSTAB_DC */
@@ -150,7 +160,8 @@ typedef struct {
     int max_iter;      /* cap on inner iterations summed over outer cycles */
     int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */
     double inner_tol;  /* relative reduction asked of each inner solve (e.g. 1e-5) */
-    int rhs_block;     /* right-hand sides per batched launch; 0 = tuned default */
+    int rhs_block;     /* right-hand sides per batched launch; 0 = the autotuned block for
+                        * inner_prec if disco_autotune ran, else 16 */
     int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
     int check_every;   /* iterations between host convergence checks (0 = default) */
 } disco_solver_params;
@@ -249,6 +260,14 @@ long long disco_last_solves(const disco_ctx* ctx);
 int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, const void* L_blk, const void* Lt_blk,
                      int ncfg, int T, const int* y0_set, int ny0, int vev_mode, void* C_full, void* C_fact, void* dC,
                      void* four_terms);
+
+/* Autotuner: time a fixed number of inner BiCGStab iterations (FP32 or BF16
+ * storage, the full operator when dom is NULL) for right-hand-side blocks of
+ * 4, 8, 16 and 32 on device-generated random sources, and keep the block with
+ * the lowest cost per right-hand side and iteration for later solves with
+ * rhs_block = 0.  best (host) receives it; cost_us (host, 4 entries, may be
+ * NULL) the measured microseconds per right-hand side and iteration. */
+int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int* best, double* cost_us);
 
 /* ---------------------------------------------------------------- profiling
  * Per-kernel-family timing of launches made while profiling is on, measured

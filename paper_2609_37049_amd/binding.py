@@ -23,6 +23,7 @@ CGNR_F64, BICGSTAB_DC = 0, 1
 K_STENCIL = 0
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
 K_MFMA = 1
+OPT_GRAPHS, OPT_STAGE = 1, 2
 
 
 class DiscoError(RuntimeError):
@@ -78,6 +79,8 @@ _SIGS.update({
     "disco_perambulators_tt": ([P, P, P, I, ctypes.c_ulonglong, ctypes.POINTER(SolverParams), P,
                                 ctypes.POINTER(SolverStats)], I),
     "disco_profile_stride": ([P, I], I),
+    "disco_set_option": ([P, I, I], I),
+    "disco_autotune": ([P, P, I, ctypes.POINTER(I), P], I),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
 })
 _OPTIONAL = {}
@@ -324,6 +327,16 @@ class Context:
         self._chk(lib().disco_perambulators_tt(self.h, None if dom is None else dom.h, _dptr(Vev), Vev.shape[1],
                                                int(tmask), ctypes.byref(params), _dptr(tau), ctypes.byref(agg)))
         return agg
+
+    def set_option(self, option, value):
+        self._chk(lib().disco_set_option(self.h, int(option), int(value)))
+
+    def autotune(self, inner_prec=F32, dom: Domains | None = None):
+        best = ctypes.c_int(0)
+        cost = np.zeros(4, dtype=np.float64)
+        self._chk(lib().disco_autotune(self.h, None if dom is None else dom.h, int(inner_prec), ctypes.byref(best),
+                                       cost.ctypes.data_as(P)))
+        return best.value, dict(zip((4, 8, 16, 32), cost))
 
     def last_solves(self):
         return int(lib().disco_last_solves(self.h))

@@ -97,6 +97,15 @@ struct disco_ctx {
     // named, grow-only device workspaces
     std::map<std::string, std::pair<void*, size_t>> ws;
 
+    // options
+    int opt_graphs = 1;   // capture inner Krylov iteration chunks as HIP graphs
+    int opt_stage = -1;   // LDS staging of links/clover in the stencil: -1 auto, 0 off, 1 on
+    // graph cache: key -> executable graph; private capture stream
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
+    // autotuned right-hand-side block per inner precision (0 = not tuned)
+    int tuned_block[3] = {0, 0, 0};
+
     // right-hand sides solved by the last distillation driver call (packed count)
     long long last_solves = 0;
 

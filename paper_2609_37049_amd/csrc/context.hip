@@ -300,6 +300,8 @@ int disco_destroy(disco_ctx* ctx) {
     hipFree(ctx->A64);
     hipFree(ctx->A32);
     hipFree(ctx->d_trav);
+    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     for (auto& r : ctx->prof) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -434,6 +436,21 @@ int disco_domains_destroy(disco_domains* d) {
 }
 
 long long disco_last_solves(const disco_ctx* ctx) { return ctx ? ctx->last_solves : -1; }
+
+int disco_set_option(disco_ctx* ctx, int option, int value) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        if (option == DISCO_OPT_GRAPHS) {
+            REQUIRE(value == 0 || value == 1, DISCO_EINVAL, "graphs option is 0 or 1");
+            ctx->opt_graphs = value;
+        } else if (option == DISCO_OPT_STAGE) {
+            REQUIRE(value >= -1 && value <= 1, DISCO_EINVAL, "stage option is -1, 0 or 1");
+            ctx->opt_stage = value;
+        } else {
+            disco_throw(DISCO_EINVAL, "unknown option %d", option);
+        }
+    });
+}
 
 int disco_profile_enable(disco_ctx* ctx, int on) {
     if (!ctx) return DISCO_EINVAL;

@@ -20,7 +20,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 namespace disco {
 void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
                   double2* x64, disco_solver_stats* st);
-int default_rhs_block(const disco_solver_params& P, int nrhs);
+int default_rhs_block(const disco_solver_params& P, int nrhs, const disco_ctx* ctx);
 }  // namespace disco
 
 namespace {
@@ -890,7 +890,7 @@ int disco_perambulators_tt(disco_ctx* ctx, const disco_domains* dom, const void*
             for (int t = 0; t < T; t++) sets.push_back(1ULL << t);
         }
         const int nrhs_set = 4 * nv;
-        const int blk = disco::default_rhs_block(*P, nrhs_set);
+        const int blk = disco::default_rhs_block(*P, nrhs_set, ctx);
         SrcSpec* specd = (SrcSpec*)ws_get(ctx, "ld_spec", sizeof(SrcSpec) * blk);
         double2* b64 = (double2*)ws_get(ctx, "ld_b64", disco::native_bytes(ctx, DISCO_F64, blk));
         double2* x64 = (double2*)ws_get(ctx, "ld_x64", disco::native_bytes(ctx, DISCO_F64, blk));

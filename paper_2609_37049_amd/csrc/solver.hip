@@ -513,18 +513,60 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
     norm2<IO>(w, r, g);
     k_sc_bicg_init<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc);
     const double tol2 = inner_tol * inner_tol;
+    // one BiCGStab iteration: 2 stencils with fused reductions, 3 vector updates, 3 scalar steps
+    auto iteration = [&]() {
+        stencil(w, prec, 0, p, v, nullptr, rh, mask, disco::EPI_DOTAUX);
+        k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+        hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
+        stencil(w, prec, 0, s, t, nullptr, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN);
+        k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+        hipLaunchKernelGGL(k_bicg_xr<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, r, rh, g, w.sc, w.part);
+        k_sc_bicg_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
+        hipLaunchKernelGGL(k_bicg_p<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, r, v, g, w.sc);
+    };
+    // A chunk of check_every iterations is captured once as a graph and replayed
+    // between the host's convergence reads (eager when profiling or disabled).
+    hipGraphExec_t exec = nullptr;
+    if (ctx->opt_graphs && !ctx->prof_on && check_every > 1) {
+        char key[512];
+        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g", prec, w.n, check_every, (void*)mask,
+                 r, rh, p, v, s, t, e, (void*)w.sc, (void*)w.part, tol2);
+        auto itg = ctx->graphs.find(key);
+        if (itg != ctx->graphs.end()) {
+            exec = itg->second;
+        } else {
+            if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            // work already queued on the caller's stream must not be reordered around the capture
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            hipStream_t user = ctx->stream;
+            ctx->stream = ctx->cap_stream;
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < check_every; k++) iteration();
+            } catch (...) {
+                hipGraph_t dead = nullptr;
+                (void)hipStreamEndCapture(ctx->cap_stream, &dead);
+                if (dead) (void)hipGraphDestroy(dead);
+                ctx->stream = user;
+                throw;
+            }
+            hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+            ctx->stream = user;
+            HIPCHK(ec);
+            hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(ei);
+            ctx->graphs[key] = exec;
+        }
+    }
     int it = 0;
     while (it < max_iter) {
-        for (int k = 0; k < check_every && it < max_iter; k++, it++) {
-            stencil(w, prec, 0, p, v, nullptr, rh, mask, disco::EPI_DOTAUX);
-            k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
-            hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
-            stencil(w, prec, 0, s, t, nullptr, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN);
-            k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
-            hipLaunchKernelGGL(k_bicg_xr<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, r, rh, g, w.sc,
-                               w.part);
-            k_sc_bicg_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
-            hipLaunchKernelGGL(k_bicg_p<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, r, v, g, w.sc);
+        if (exec && max_iter - it >= check_every) {
+            HIPCHK(hipGraphLaunch(exec, ctx->stream));
+            it += check_every;
+        } else {
+            for (int k = 0; k < check_every && it < max_iter; k++, it++) iteration();
         }
         HIPCHK(hipGetLastError());
         pull(w);
@@ -688,12 +730,82 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
     }
 }
 
-int default_rhs_block(const disco_solver_params& P, int nrhs) {
-    int b = P.rhs_block > 0 ? P.rhs_block : 16;
+int default_rhs_block(const disco_solver_params& P, int nrhs, const disco_ctx* ctx) {
+    int b = P.rhs_block;
+    if (b <= 0 && ctx && P.method == DISCO_BICGSTAB_DC && P.inner_prec >= 0 && P.inner_prec <= 2)
+        b = ctx->tuned_block[P.inner_prec];
+    if (b <= 0) b = 16;
     return std::max(1, std::min({b, nrhs, 64}));
 }
 
 }  // namespace disco
+
+namespace {
+__global__ void k_rand_spinor(double2* b, long n, unsigned long long seed) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        unsigned long long z = seed + 0x9e3779b97f4a7c15ULL * (unsigned long long)(i + 1);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        b[i] = make_double2((double)(z >> 40) / 16777216.0 - 0.5, (double)(z & 0xffffff) / 16777216.0 - 0.5);
+    }
+}
+}  // namespace
+
+extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int* best, double* cost_us) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(inner_prec == DISCO_F32 || inner_prec == DISCO_BF16, DISCO_EINVAL, "tune FP32 or BF16 storage");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "autotune before clover_setup");
+        REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
+        activate(ctx);
+        const int cand[4] = {4, 8, 16, 32};
+        const int iters = 20;
+        double cost[4];
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (int c = 0; c < 4; c++) {
+            const int n = cand[c];
+            Work w;
+            w.ctx = ctx;
+            w.n = n;
+            w.V = ctx->V;
+            w.nsb = disco::stencil_nsb(ctx, n);
+            w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
+            VecGeo g = vgeo(ctx->V, DISCO_F64, n);
+            w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * (size_t)std::max(w.nsb, g.nb) * 3 * n);
+            HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
+            double2* b64 = (double2*)ws_get(ctx, "tune_b", disco::native_bytes(ctx, DISCO_F64, n));
+            void* rin = ws_get(ctx, "dc_rin", disco::native_bytes(ctx, inner_prec, n));
+            void* e = ws_get(ctx, "dc_e", disco::native_bytes(ctx, inner_prec, n));
+            k_rand_spinor<<<2048, 256, 0, ctx->stream>>>(b64, ctx->V * 12L * n, 0x7157ULL + n);
+            if (inner_prec == DISCO_F32) copy_scale<IO64, IO32>(w, b64, rin, 0);
+            else copy_scale<IO64, IOBF>(w, b64, rin, 0);
+            const uint8_t* mask = dom ? dom->d_mask : nullptr;
+            // one untimed pass (graph capture, caches), then the timed one
+            for (int rep = 0; rep < 2; rep++) {
+                HIPCHK(hipEventRecord(e0, ctx->stream));
+                if (inner_prec == DISCO_F32) bicg_run<IO32>(w, DISCO_F32, rin, e, mask, 0.0, iters, 10);
+                else bicg_run<IOBF>(w, DISCO_BF16, rin, e, mask, 0.0, iters, 10);
+                HIPCHK(hipEventRecord(e1, ctx->stream));
+                HIPCHK(hipEventSynchronize(e1));
+            }
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            cost[c] = 1e3 * ms / (double)(n * iters);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        int bi = 0;
+        for (int c = 1; c < 4; c++)
+            if (cost[c] < cost[bi]) bi = c;
+        ctx->tuned_block[inner_prec] = cand[bi];
+        if (best) *best = cand[bi];
+        if (cost_us)
+            for (int c = 0; c < 4; c++) cost_us[c] = cost[c];
+    });
+}
 
 extern "C" int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params* p, int nrhs,
                                      const void* b, void* x, disco_solver_stats* stats) {
@@ -707,7 +819,7 @@ extern "C" int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, c
         REQUIRE(ctx->have_clover, DISCO_ESTATE, "solve before clover_setup");
         activate(ctx);
         if (nrhs == 0) return;
-        const int blk = disco::default_rhs_block(*p, nrhs);
+        const int blk = disco::default_rhs_block(*p, nrhs, ctx);
         const size_t field = (size_t)ctx->V * 12 * sizeof(double2);
         std::vector<disco_solver_stats> st(blk);
         for (int r0 = 0; r0 < nrhs; r0 += blk) {

@@ -41,6 +41,7 @@ struct StencilArgs {
     int spb;   // sites per block
     int n;     // right-hand sides in the block
     int dagger;
+    int stage; // LDS staging requested (applies to FP32 links with at most kStageSites sites per block)
 };
 
 // ---- spin projection (1 - gamma_mu) [FWD] or (1 + gamma_mu) [BWD], chiral basis
@@ -407,7 +408,7 @@ __global__ void k_from_native(const void* __restrict__ in, double2* __restrict__
 template <class IO, int EPI>
 void launch_one(disco_ctx* ctx, const StencilArgs& a) {
     const dim3 grid(xcd_grid(a.nsb)), block(kStencilBlock);
-    const bool stage = sizeof(typename IO::T) == 4 && a.spb <= kStageSites && !getenv("DISCO_NO_STAGE");
+    const bool stage = sizeof(typename IO::T) == 4 && a.spb <= kStageSites && a.stage;
     if (stage) {
         const size_t shm = (size_t)a.spb * (kStageLinkBytes + kStageCloverBytes);
         if (a.in.buf)
@@ -519,6 +520,8 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     a.spb = stencil_spb(c.nrhs);
     a.nsb = stencil_nsb(ctx, c.nrhs);
     a.dagger = c.dagger;
+    // staging pays once a site has 16 or more lanes sharing its links
+    a.stage = ctx->opt_stage == 1 || (ctx->opt_stage == -1 && c.nrhs >= 16);
     double sp = c.prec == DISCO_F64 ? 8 : c.prec == DISCO_F32 ? 4 : 2;  // bytes per spinor real
     double sg = c.prec == DISCO_F64 ? 8 : 4;                             // bytes per link/clover real
     int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & EPI_DOTAUX) ? 1 : 0);

@@ -130,3 +130,60 @@ def test_full_size_mixed_precision_solve(disco):
             rr = _true_rel_res(U, A, dims, pre.kappa, b[:3], x[:3], c)
             assert rr.max() <= 1e-10 * 1.01, rr
             assert all(s.converged for s in st)
+
+
+def test_graph_replays_equal_eager(disco):
+    """Inner iterations captured as HIP graphs give bitwise the same solutions
+    as eager launches: the chunk graph is replayed many times per solve, with
+    host reads and FP64 outer-residual work between replays."""
+    pre = synth.PRESETS["plain_4x4x4x4"]
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.3, 21)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(0.125, 1.3)
+    V = int(np.prod(dims))
+    b = ctx.dev(synth.random_spinor(V, 24, 22))
+    out = {}
+    for g in (0, 1):
+        ctx.set_option(disco.OPT_GRAPHS, g)
+        for inner in (disco.F32, disco.BF16):
+            P = ctx.params(tol=1e-11, inner_prec=inner, rhs_block=8, check_every=5)
+            x, st = ctx.solve_multi_rhs(b, P)
+            out[(g, inner)] = (x.cpu().numpy(), [s.iters for s in st])
+    for inner in (disco.F32, disco.BF16):
+        assert out[(0, inner)][1] == out[(1, inner)][1]
+        assert np.array_equal(out[(0, inner)][0], out[(1, inner)][0])
+    ctx.set_option(disco.OPT_GRAPHS, 1)
+
+
+def test_stage_option_same_operator(disco):
+    dims = (8, 8, 4, 8)
+    U = synth.gauge_field(dims, 0.3, 23)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(0.12, 1.1)
+    V = int(np.prod(dims))
+    psi = synth.random_spinor(V, 16, 24)
+    res = {}
+    for stage in (0, 1):
+        ctx.set_option(disco.OPT_STAGE, stage)
+        res[stage] = ctx.dirac_apply(ctx.dev(psi), disco.F32).cpu().numpy()
+    ctx.set_option(disco.OPT_STAGE, -1)
+    assert np.array_equal(res[0], res[1])
+
+
+def test_autotune_picks_a_block(disco):
+    dims = (8, 8, 8, 16)
+    U = synth.gauge_field(dims, 0.25, 25)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(0.125, 1.5)
+    best, cost = ctx.autotune(disco.BF16)
+    assert best in (4, 8, 16, 32)
+    assert all(c > 0 for c in cost.values()) and cost[best] == min(cost.values())
+    V = int(np.prod(dims))
+    b = synth.random_spinor(V, 5, 26)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), ctx.params(tol=1e-10, inner_prec=disco.BF16, rhs_block=0))
+    A = oracle.clover(U, dims, 0.125, 1.5)
+    assert _true_rel_res(U, A, dims, 0.125, b, x.cpu().numpy()).max() <= 1e-10 * 1.01
