@@ -192,7 +192,7 @@ def main():
     # roofline, with the algorithmic HBM rate (the metric's GB/s) beside it.
     roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
             "unit": "TFLOP/s", "frac": round(tflops / VALU_FP32_PEAK_TFLOPS, 4),
-            "traffic": load_traffic(kernel_tag),
+            "traffic": load_traffic("%s/n%d" % (kernel_tag, blk)),
             "hbm_gbps": round(gbps, 1), "hbm_peak_gbps": HBM_PEAK_GBPS, "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
             "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, %d RHS per launch)" % blk,
             "avg_launch_ms": round(avg_ms, 5), "launches_timed": nl,
