@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct disco_ctx disco_ctx;
 typedef struct disco_domains disco_domains;
+typedef struct disco_net disco_net;
 
 enum {
     DISCO_OK = 0,
@@ -70,7 +71,9 @@ enum { DISCO_G_1 = 0, DISCO_G_5 = 1, DISCO_G_X = 2, DISCO_G_Y = 3, DISCO_G_Z = 4
 /* solver methods */
 enum {
     DISCO_CGNR_F64 = 0,    /* conjugate gradients on D^+ D, all FP64 (plain judge) */
-    DISCO_BICGSTAB_DC = 1  /* BiCGStab in inner_prec inside FP64 defect correction */
+    DISCO_BICGSTAB_DC = 1, /* BiCGStab in inner_prec inside FP64 defect correction */
+    DISCO_FGMRES_NN = 2    /* flexible GMRES(restart), FP32 Krylov basis, preconditioned by a
+                            * trained network (params.net), inside FP64 defect correction */
 };
 
 /* ---------------------------------------------------------------- context */
@@ -164,6 +167,8 @@ typedef struct {
                         * inner_prec if disco_autotune ran, else 16 */
     int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
     int check_every;   /* iterations between host convergence checks (0 = default) */
+    int restart;       /* FGMRES_NN: Krylov vectors per cycle (1..32, 0 = 16) */
+    const disco_net* net; /* FGMRES_NN: the preconditioner (required) */
 } disco_solver_params;
 
 typedef struct {
@@ -269,6 +274,62 @@ int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, co
  * NULL) the measured microseconds per right-hand side and iteration. */
 int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int* best, double* cost_us);
 
+/* ---------------------------------------------------------------- learned preconditioner
+ * Not part of the paper, which only needs D^-1: the production solver's own
+ * approximation of D^-1, judged only through the FP64 true residual of the
+ * solves it preconditions.  A gauge-covariant convolutional network of three
+ * layers with channels 1 -> 16 -> 16 -> 1, no nonlinearity:
+ *   out_o(x) = sum_i sum_{d in {-1,0,1}^4} W[d][o][i] . T_d(x) psi_i(x + d)
+ * W[d][o][i] is a complex 4x4 matrix on the spin index; T_d(x) is the colour
+ * transporter along the axis-ordered path from x to x + d (|d_x| hops in x,
+ * then y, z, t; a forward hop from y takes U_mu(y), a backward hop
+ * U_mu(y - mu)^+, and a hop across the wrap the boundary phase bc[mu]).
+ * Offsets are numbered k = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1).
+ * Weights: FP32, layers in order, each [81][C_out][C_in][4][4] complex stored
+ * as (re, im) pairs: 2 * 81 * 16 * (16 + 256 + 16) floats = 746496.
+ * Activations are BF16 with FP32 accumulation (matrix cores).
+ * The lattice needs Lx, Ly divisible by 4 and Lz, Lt by 2. */
+/* Create a network on the context's gauge field (tabulates the 81
+ * transporters per site, 5.8 KB per site).  Initial weights: identity through
+ * channel 0 of each layer plus Gaussian noise of standard deviation 0.01 from
+ * `seed`.  channels must be 16.  ESTATE before disco_gauge_set.  The network
+ * keeps the transporters of the gauge field current at creation. */
+int disco_net_create(disco_ctx* ctx, int channels, unsigned long long seed, disco_net** out);
+int disco_net_destroy(disco_net* net);
+/* number of floats of the packed weights */
+long long disco_net_weights_count(const disco_net* net);
+int disco_net_set_weights(disco_net* net, const float* w, int where);
+int disco_net_get_weights(disco_net* net, float* w, int where);
+/* out = N(in) for nrhs fields [nrhs][V][4][3] complex128 (device). */
+int disco_net_apply(disco_net* net, int nrhs, const void* in, void* out);
+/* Gradients of the real function L with dL/dRe(out) + i dL/dIm(out) = grad_out
+ * (device [nrhs][V][4][3] complex128) at inputs in (same layout, nrhs <= 64):
+ * grad_w (device, weights layout) = dL/dRe(W) + i dL/dIm(W) summed over the
+ * right-hand sides; grad_in (device, may be NULL) = dL/dRe(in) + i dL/dIm(in). */
+int disco_net_backward(disco_net* net, int nrhs, const void* in, const void* grad_out, float* grad_w, void* grad_in);
+
+typedef struct {
+    int npairs;          /* (residual, error) pairs to generate (multiple of nsnap and batch) */
+    int nsnap;           /* pairs per source: one per truncated solve (1..8) */
+    int snap_iters[8];   /* inner iterations of each truncated solve (0: x_k = 0, i.e. e = x*) */
+    int batch;           /* pairs per Adam step (1..16) */
+    int steps;           /* Adam steps */
+    double lr;           /* Adam learning rate */
+    unsigned long long seed;
+} disco_train_params;
+typedef struct {
+    int pairs, steps;
+    double first_loss;   /* mean |N(r) - e|^2 of the first mini-batch (|e| = 1) */
+    double final_loss;   /* mean over the last quarter of the steps (at most one epoch) */
+    double gen_seconds, train_seconds;
+} disco_train_stats;
+/* Train on pairs the solver generates on this context's gauge field: Gaussian
+ * sources b, converged x* (BiCGStab-DC to 1e-9), truncated solves x_k, error
+ * e = x* - x_k, residual r = D e (FP64), each pair scaled to |e| = 1.  Loss
+ * (1/B) sum_p |N(r_p) - e_p|^2, Adam (beta 0.9, 0.999, eps 1e-8) with this
+ * library's own forward and backward kernels. */
+int disco_net_train(disco_net* net, const disco_train_params* p, disco_train_stats* stats);
+
 /* ---------------------------------------------------------------- profiling
  * Per-kernel-family timing of launches made while profiling is on, measured
  * with HIP events recorded on the context's stream around each launch.
@@ -276,7 +337,9 @@ int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int
  * bytes of those launches (each input/output spinor, the links and the clover
  * term counted once per site); 10, 11, 12 = the same split by storage
  * precision (FP64, FP32, BF16); 1 = FP64 matrix-core contraction
- * (perambulator, eigensolver Gram matrices): bytes holds the flop count. */
+ * (perambulator, eigensolver Gram matrices): bytes holds the flop count;
+ * 2 = network layers (BF16 matrix cores): bytes holds the flop count. */
+enum { DISCO_KERNEL_STENCIL = 0, DISCO_KERNEL_MFMA64 = 1, DISCO_KERNEL_NN = 2 };
 int disco_profile_enable(disco_ctx* ctx, int on);
 /* Time only every `stride`-th profiled launch of each family (default 1). */
 int disco_profile_stride(disco_ctx* ctx, int stride);

@@ -19,8 +19,9 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -
 F64, F32, BF16 = 0, 1, 2
 HOST, DEVICE = 0, 1
 G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
-CGNR_F64, BICGSTAB_DC = 0, 1
+CGNR_F64, BICGSTAB_DC, FGMRES_NN = 0, 1, 2
 K_STENCIL = 0
+K_NN = 2
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
 K_MFMA = 1
 OPT_GRAPHS, OPT_STAGE = 1, 2
@@ -35,12 +36,24 @@ class DiscoError(RuntimeError):
 class SolverParams(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_block", ctypes.c_int),
-                ("fallback", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("check_every", ctypes.c_int), ("restart", ctypes.c_int),
+                ("net", ctypes.c_void_p)]
 
 
 class SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("converged", ctypes.c_int), ("true_rel_residual", ctypes.c_double)]
+
+
+class TrainParams(ctypes.Structure):
+    _fields_ = [("npairs", ctypes.c_int), ("nsnap", ctypes.c_int), ("snap_iters", ctypes.c_int * 8),
+                ("batch", ctypes.c_int), ("steps", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int), ("steps", ctypes.c_int), ("first_loss", ctypes.c_double),
+                ("final_loss", ctypes.c_double), ("gen_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +95,14 @@ _SIGS.update({
     "disco_set_option": ([P, I, I], I),
     "disco_autotune": ([P, P, I, ctypes.POINTER(I), P], I),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
+    "disco_net_create": ([P, I, ctypes.c_ulonglong, P], I),
+    "disco_net_destroy": ([P], I),
+    "disco_net_weights_count": ([P], LL),
+    "disco_net_set_weights": ([P, P, I], I),
+    "disco_net_get_weights": ([P, P, I], I),
+    "disco_net_apply": ([P, I, P, P], I),
+    "disco_net_backward": ([P, I, P, P, P, P], I),
+    "disco_net_train": ([P, ctypes.POINTER(TrainParams), ctypes.POINTER(TrainStats)], I),
 })
 _OPTIONAL = {}
 
@@ -144,6 +165,65 @@ class Domains:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The gauge-covariant network (learned preconditioner) on a context's gauge field."""
+
+    def __init__(self, ctx: "Context", channels: int = 16, seed: int = 1):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._chk(lib().disco_net_create(ctx.h, int(channels), ctypes.c_ulonglong(seed), ctypes.byref(h)))
+        self.h = h
+        self.nw = int(lib().disco_net_weights_count(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().disco_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.nw, dtype=np.float32)
+        self.ctx._chk(lib().disco_net_get_weights(self.h, w.ctypes.data_as(P), HOST))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        if w.size != self.nw:
+            raise ValueError("expected %d weights" % self.nw)
+        self.ctx._chk(lib().disco_net_set_weights(self.h, w.ctypes.data_as(P), HOST))
+
+    def apply(self, x):
+        out = _torch().empty_like(x)
+        self.ctx._chk(lib().disco_net_apply(self.h, x.shape[0], _dptr(x), _dptr(out)))
+        return out
+
+    def backward(self, x, grad_out, want_grad_in=True):
+        torch = _torch()
+        gw = torch.empty(self.nw, dtype=torch.float32, device=x.device)
+        gi = torch.empty_like(x) if want_grad_in else None
+        self.ctx._chk(lib().disco_net_backward(self.h, x.shape[0], _dptr(x), _dptr(grad_out), _dptr(gw), _dptr(gi)))
+        return gw, gi
+
+    def train(self, npairs, snap_iters=(0, 8, 32, 96), batch=4, steps=100, lr=1e-3, seed=1):
+        tp = TrainParams()
+        tp.npairs = int(npairs)
+        tp.nsnap = len(snap_iters)
+        for k, v in enumerate(snap_iters):
+            tp.snap_iters[k] = int(v)
+        tp.batch = int(batch)
+        tp.steps = int(steps)
+        tp.lr = float(lr)
+        tp.seed = int(seed)
+        ts = TrainStats()
+        self.ctx._chk(lib().disco_net_train(self.h, ctypes.byref(tp), ctypes.byref(ts)))
+        return ts
 
 
 class Context:
@@ -254,8 +334,11 @@ class Context:
     # -- solver
     @staticmethod
     def params(method=BICGSTAB_DC, tol=1e-10, max_iter=0, inner_prec=F32, inner_tol=0.0, rhs_block=0,
-               fallback=1, check_every=0) -> SolverParams:
-        return SolverParams(method, tol, max_iter, inner_prec, inner_tol, rhs_block, fallback, check_every)
+               fallback=1, check_every=0, restart=0, net=None) -> SolverParams:
+        p = SolverParams(method, tol, max_iter, inner_prec, inner_tol, rhs_block, fallback, check_every, restart,
+                         None if net is None else net.h.value)
+        p._net = net  # keep the network alive while the parameters are in use
+        return p
 
     def solve_multi_rhs(self, b, params: SolverParams, dom: Domains | None = None, x=None, allow_noconv=False):
         n = b.shape[0]

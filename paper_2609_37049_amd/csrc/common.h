@@ -254,4 +254,9 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c);
 size_t native_bytes(const disco_ctx* ctx, int prec, int nrhs);
 void to_native(disco_ctx* ctx, int prec, int nrhs, const void* in, void* out);
 void from_native(disco_ctx* ctx, int prec, int nrhs, const void* in, void* out);
+void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
+                  double2* x64, disco_solver_stats* st);
+// learned preconditioner: z = N(v) on native FP32 blocks of n right-hand sides
+void net_apply_native32(disco_net* net, int n, const void* in32, void* out32);
+disco_ctx* net_ctx(const disco_net* net);
 }  // namespace disco

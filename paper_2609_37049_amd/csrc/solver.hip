@@ -6,6 +6,11 @@
 //     normalised defect, inside an FP64 defect-correction loop that keeps x,
 //     recomputes r = b - D x with the FP64 operator, and decides convergence
 //     on that true residual.  Optional FP64 CGNR fallback.
+//   FGMRES-NN: flexible GMRES(m) with an FP32 Krylov basis, right-
+//     preconditioned by the trained network (z_j = N(v_j)), inside the same
+//     FP64 defect correction and fallback.  Classical Gram-Schmidt with one
+//     re-orthogonalisation on the device; the small Hessenberg least-squares
+//     problem of each right-hand side (complex Givens rotations) on the host.
 //
 // Every Krylov scalar lives on the device: reductions produce deterministic
 // per-block partial sums that one small kernel per right-hand side folds in a
@@ -19,6 +24,7 @@
 // right-hand side across its grid-stride loop.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 
 #include "spinor_io.h"
@@ -670,6 +676,235 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
     fill_stats(w, P, iters, outer, fb, st);
 }
 
+// --------------------------------------------------------------- FGMRES
+// partial sums of <v_k, w> (k = k0 .. k0+NQ-1 < kn) per right-hand side, FP32 native blocks
+template <int NQ>
+__global__ void k_mdot32(const float4* __restrict__ basis, long vst, int k0, int kn, const float4* __restrict__ w,
+                         VecGeo g, double2* part) {
+    double acc[2 * NQ];
+#pragma unroll
+    for (int q = 0; q < 2 * NQ; q++) acc[q] = 0;
+    VEC_LOOP(g) {
+        const float4 b = w[i];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            if (k0 + q < kn) {
+                const float4 a = basis[(size_t)(k0 + q) * vst + i];
+                acc[2 * q] += (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+                acc[2 * q + 1] += (double)a.x * b.y - (double)a.y * b.x + (double)a.z * b.w - (double)a.w * b.z;
+            }
+        }
+    }
+    rhs_partials<NQ>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
+}
+template <int NQ>
+__global__ void k_fold_dots(const double2* part, int nparts, int k0, int kn, int n, double2* hd) {
+    cd q[NQ];
+    fold<NQ>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+#pragma unroll
+    for (int k = 0; k < NQ; k++)
+        if (k0 + k < kn) hd[(size_t)(k0 + k) * n + blockIdx.x] = make_double2(q[k].re, q[k].im);
+}
+__global__ void k_fold_norm(const double2* part, int nparts, double* nd) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x == 0) nd[blockIdx.x] = q[0].re;
+}
+// w += sign * sum_{k < kn} c[k][r] basis_k
+__global__ void k_maxpy32(const float4* __restrict__ basis, long vst, int kn, const double2* __restrict__ c,
+                          float4* __restrict__ w, VecGeo g, float sign) {
+    const int r = threadIdx.x % g.n;
+    VEC_LOOP(g) {
+        float4 acc = w[i];
+        for (int k = 0; k < kn; k++) {
+            const double2 h = c[(size_t)k * g.n + r];
+            const float hr = sign * (float)h.x, hi = sign * (float)h.y;
+            const float4 a = basis[(size_t)k * vst + i];
+            acc.x = fmaf(hr, a.x, fmaf(-hi, a.y, acc.x));
+            acc.y = fmaf(hr, a.y, fmaf(hi, a.x, acc.y));
+            acc.z = fmaf(hr, a.z, fmaf(-hi, a.w, acc.z));
+            acc.w = fmaf(hr, a.w, fmaf(hi, a.z, acc.w));
+        }
+        w[i] = acc;
+    }
+}
+// v = w / sqrt(nd[r]) (0 when the norm vanishes)
+__global__ void k_scale32(const float4* __restrict__ w, float4* __restrict__ v, VecGeo g, const double* nd) {
+    const int r = threadIdx.x % g.n;
+    const double q = nd[r];
+    const float f = q > 1e-60 ? (float)(1.0 / sqrt(q)) : 0.f;
+    VEC_LOOP(g) {
+        const float4 a = w[i];
+        v[i] = make_float4(f * a.x, f * a.y, f * a.z, f * a.w);
+    }
+}
+
+// One FGMRES(m) cycle on D e = rin (FP32 native, normalised defect), e = sum_j y_j z_j.
+// Returns the number of Arnoldi steps.
+static int fgmres_cycle(Work& w, const disco_solver_params& P, const void* rin, void* e, const uint8_t* mask,
+                        double inner_tol) {
+    disco_ctx* ctx = w.ctx;
+    disco_net* net = const_cast<disco_net*>(P.net);
+    const int m = P.restart > 0 ? P.restart : 16;
+    const int n = w.n;
+    VecGeo g = vgeo(w.V, DISCO_F32, n);
+    const size_t vb = disco::native_bytes(ctx, DISCO_F32, n);
+    const long vst = g.total;  // float4 units per vector
+    float4* Vb = (float4*)ws_get(ctx, "fg_V", vb * (m + 1));
+    float4* Zb = (float4*)ws_get(ctx, "fg_Z", vb * m);
+    float4* wv = (float4*)ws_get(ctx, "fg_w", vb);
+    double2* h1 = (double2*)ws_get(ctx, "fg_h1", sizeof(double2) * (m + 1) * n);
+    double2* h2 = (double2*)ws_get(ctx, "fg_h2", sizeof(double2) * (m + 1) * n);
+    double* nd = (double*)ws_get(ctx, "fg_nd", sizeof(double) * n);
+    double2* yd = (double2*)ws_get(ctx, "fg_y", sizeof(double2) * m * n);
+    typedef std::complex<double> C;
+    // v_0 = rin / |rin|, beta = |rin|
+    norm2<IO32>(w, rin, g);
+    k_fold_norm<<<n, 256, 0, ctx->stream>>>(w.part, g.nb, nd);
+    hipLaunchKernelGGL(k_scale32, dim3(g.nb), dim3(g.bd), 0, ctx->stream, (const float4*)rin, Vb, g, nd);
+    std::vector<double> hn(n);
+    HIPCHK(hipMemcpyAsync(hn.data(), nd, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<std::vector<C>> R(n, std::vector<C>((size_t)m * m)), gv(n, std::vector<C>(m + 1));
+    std::vector<std::vector<double>> cs(n, std::vector<double>(m));
+    std::vector<std::vector<C>> sn(n, std::vector<C>(m));
+    for (int r = 0; r < n; r++) gv[r][0] = std::sqrt(std::max(hn[r], 0.0));
+    std::vector<double2> hh1((size_t)(m + 1) * n), hh2((size_t)(m + 1) * n);
+    int steps = 0;
+    for (int j = 0; j < m; j++) {
+        float4* vj = Vb + (size_t)j * vst;
+        float4* zj = Zb + (size_t)j * vst;
+        disco::net_apply_native32(net, n, vj, zj);
+        stencil(w, DISCO_F32, 0, zj, wv, nullptr, nullptr, mask, disco::EPI_NONE);
+        double2* hp[2] = {h1, h2};
+        for (int pass = 0; pass < 2; pass++) {
+            for (int k0 = 0; k0 <= j; k0 += 4) {
+                hipLaunchKernelGGL(k_mdot32<4>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, Vb, vst, k0, j + 1, wv, g,
+                                   w.part);
+                k_fold_dots<4><<<n, 256, 0, ctx->stream>>>(w.part, g.nb, k0, j + 1, n, hp[pass]);
+            }
+            hipLaunchKernelGGL(k_maxpy32, dim3(g.nb), dim3(g.bd), 0, ctx->stream, Vb, vst, j + 1, hp[pass], wv, g,
+                               -1.0f);
+        }
+        norm2<IO32>(w, wv, g);
+        k_fold_norm<<<n, 256, 0, ctx->stream>>>(w.part, g.nb, nd);
+        hipLaunchKernelGGL(k_scale32, dim3(g.nb), dim3(g.bd), 0, ctx->stream, wv, Vb + (size_t)(j + 1) * vst, g, nd);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hh1.data(), h1, sizeof(double2) * (j + 1) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(hh2.data(), h2, sizeof(double2) * (j + 1) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(hn.data(), nd, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        steps++;
+        bool all = true;
+        for (int r = 0; r < n; r++) {
+            std::vector<C> col(j + 2);
+            for (int k = 0; k <= j; k++) {
+                const double2 a = hh1[(size_t)k * n + r], b = hh2[(size_t)k * n + r];
+                col[k] = C(a.x + b.x, a.y + b.y);
+            }
+            col[j + 1] = std::sqrt(std::max(hn[r], 0.0));
+            for (int k = 0; k < j; k++) {  // earlier rotations
+                const C t = cs[r][k] * col[k] + sn[r][k] * col[k + 1];
+                col[k + 1] = -std::conj(sn[r][k]) * col[k] + cs[r][k] * col[k + 1];
+                col[k] = t;
+            }
+            const C a = col[j], b = col[j + 1];
+            const double rr = std::sqrt(std::norm(a) + std::norm(b));
+            double c = 1.0;
+            C s = 0.0;
+            if (rr > 0) {
+                const double aa = std::abs(a);
+                c = aa / rr;
+                s = (aa > 0 ? a / aa : C(1.0)) * std::conj(b) / rr;
+            }
+            cs[r][j] = c;
+            sn[r][j] = s;
+            col[j] = c * a + s * b;
+            for (int k = 0; k <= j; k++) R[r][(size_t)k * m + j] = col[k];
+            gv[r][j + 1] = -std::conj(s) * gv[r][j];
+            gv[r][j] = c * gv[r][j];
+            const double beta = std::abs(gv[r][0]);
+            all &= beta == 0.0 || std::abs(gv[r][j + 1]) <= inner_tol * beta;
+        }
+        if (all) break;
+    }
+    // y = R^-1 g (back substitution), e = sum_j y_j z_j
+    const int kk = steps;
+    std::vector<double2> hy((size_t)m * n);
+    for (int r = 0; r < n; r++) {
+        std::vector<C> y(kk);
+        for (int i = kk - 1; i >= 0; i--) {
+            C acc = gv[r][i];
+            for (int k = i + 1; k < kk; k++) acc -= R[r][(size_t)i * m + k] * y[k];
+            const C d = R[r][(size_t)i * m + i];
+            y[i] = std::abs(d) > 0 ? acc / d : C(0.0);
+        }
+        for (int i = 0; i < kk; i++) hy[(size_t)i * n + r] = make_double2(y[i].real(), y[i].imag());
+    }
+    HIPCHK(hipMemcpyAsync(yd, hy.data(), sizeof(double2) * kk * n, hipMemcpyHostToDevice, ctx->stream));
+    k_zero<IO32><<<1024, 256, 0, ctx->stream>>>(e, g.total);
+    hipLaunchKernelGGL(k_maxpy32, dim3(g.nb), dim3(g.bd), 0, ctx->stream, Zb, vst, kk, yd, (float4*)e, g, 1.0f);
+    HIPCHK(hipGetLastError());
+    return steps;
+}
+
+static void fgmres_solve(Work& w, const disco_solver_params& P, const double2* b64, double2* x64, const uint8_t* mask,
+                         disco_solver_stats* st) {
+    disco_ctx* ctx = w.ctx;
+    REQUIRE(P.net != nullptr, DISCO_EINVAL, "FGMRES_NN needs params.net");
+    REQUIRE(disco::net_ctx(P.net) == ctx, DISCO_EINVAL, "the network belongs to another context");
+    REQUIRE(P.restart >= 0 && P.restart <= 32, DISCO_EINVAL, "restart must be 0..32");
+    size_t nb64 = disco::native_bytes(ctx, DISCO_F64, w.n);
+    size_t nbp = disco::native_bytes(ctx, DISCO_F32, w.n);
+    double2* r64 = (double2*)ws_get(ctx, "dc_r64", nb64);
+    void* rin = ws_get(ctx, "dc_rin", nbp);
+    void* e = ws_get(ctx, "dc_e", nbp);
+    VecGeo g64 = vgeo(w.V, DISCO_F64, w.n);
+    const double tol2 = P.tol * P.tol;
+    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+    norm2<IO64>(w, b64, g64);
+    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    copy_scale<IO64, IO64>(w, b64, r64, 0);
+    int iters = 0, outer = 0;
+    const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+    const int check = P.check_every > 0 ? P.check_every : 10;
+    const double itol = P.inner_tol > 0 ? P.inner_tol : 1e-4;
+    const bool trace = getenv("DISCO_TRACE") != nullptr;
+    double last_worst = 1e300;
+    int stall = 0;
+    while (true) {
+        pull(w);
+        bool done = true;
+        double worst = 0;
+        for (auto& s : w.h) {
+            done &= s.outer_done != 0;
+            if (s.bb > 0) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+        }
+        if (trace)
+            fprintf(stderr, "[disco] fgmres outer %d: worst true rel residual %.3e, %d Arnoldi steps\n", outer, worst,
+                    iters);
+        if (done || iters >= max_iter) break;
+        stall = worst > 0.5 * last_worst ? stall + 1 : 0;
+        last_worst = worst;
+        if (stall >= 3) break;
+        outer++;
+        copy_scale<IO64, IO32>(w, r64, rin, 1);
+        iters += fgmres_cycle(w, P, rin, e, mask, itol);
+        dc_update<IO32>(w, x64, e);
+        outer_residual(w, b64, x64, r64, mask, tol2);
+    }
+    int fb = 0;
+    pull(w);
+    bool done = true;
+    for (auto& s : w.h) done &= s.outer_done != 0;
+    if (!done && P.fallback) {
+        fb = 1;
+        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, max_iter - iters), check, &iters);
+    }
+    fill_stats(w, P, iters, outer, fb, st);
+}
+
 static void cgnr_solve(Work& w, const disco_solver_params& P, const double2* b64, double2* x64, const uint8_t* mask,
                        disco_solver_stats* st) {
     disco_ctx* ctx = w.ctx;
@@ -711,7 +946,8 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
     w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
     VecGeo g = vgeo(ctx->V, DISCO_F64, n);
     size_t slots = (size_t)std::max(w.nsb, g.nb);
-    w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 3 * n);
+    // up to 4 quantities per right-hand side (the stencil epilogues use 3, FGMRES dots 4)
+    w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 4 * n);
     HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
     const uint8_t* mask = dom ? dom->d_mask : nullptr;
     if (P.method == DISCO_CGNR_F64) {
@@ -725,6 +961,8 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
             dc_solve<IO64>(w, P, DISCO_F64, b64, x64, mask, st);
         else
             disco_throw(DISCO_EINVAL, "bad inner precision %d", P.inner_prec);
+    } else if (P.method == DISCO_FGMRES_NN) {
+        fgmres_solve(w, P, b64, x64, mask, st);
     } else {
         disco_throw(DISCO_EINVAL, "unknown solver method %d", P.method);
     }
