@@ -64,6 +64,62 @@ def load_traffic(kernel_tag):
     return ent.get("bytes_per_launch")
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def solver_comparison(ctx, d, Vev, inner, tuned, T):
+    """The plain FP64 GPU solvers, the production mixed-precision batched
+    solver and the learned-preconditioner solver on the same 16 distillation
+    sources (timeslice 0, eigenvectors 0..3 x 4 spins) to true relative
+    residual 1e-10.  Not part of the timed steps."""
+    import torch
+    V, Vs = ctx.V, ctx.Vs
+    b = torch.zeros((16, V, 4, 3), dtype=torch.complex128, device="cuda:0")
+    for i in range(4):
+        for a in range(4):
+            b[4 * i + a, :Vs, a, :] = Vev[0, i]
+    out = {}
+
+    def run(name, P, nb):
+        bb = b[:nb].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.solve_multi_rhs(bb, P)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"rhs_per_s": round(nb / dt, 3), "rhs": nb, "iters": st[0].iters,
+                     "fallback_used": max(s.fallback_used for s in st),
+                     "worst_true_rel_residual": max(s.true_rel_residual for s in st)}
+        print("comparison %s: %.2f RHS/s" % (name, nb / dt), file=sys.stderr, flush=True)
+
+    run("cgnr_f64_1rhs_plain", ctx.params(method=d.CGNR_F64, tol=1e-10, rhs_block=1), 2)
+    ctx.set_option(d.OPT_EO, 0)
+    run("bicgstab_f64_1rhs_unpreconditioned", ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=d.F64,
+                                                          rhs_block=1), 2)
+    ctx.set_option(d.OPT_EO, 1)
+    run("bicgstab_f64_1rhs_even_odd", ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=d.F64, rhs_block=1), 2)
+    run("mixed_batched_bicgstab", ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=inner, rhs_block=tuned), 16)
+    net = d.Net(ctx, 16, 7)
+    t0 = time.perf_counter()
+    ts = net.train(64, snap_iters=(0, 16, 64, 192), batch=4, steps=100, lr=2e-3, seed=5)
+    train_s = time.perf_counter() - t0
+    ctx.profile_reset()
+    ctx.profile_stride(1)
+    ctx.profile_enable(True)
+    run("mixed_batched_learned_fgmres16", ctx.params(method=d.FGMRES_NN, tol=1e-10, net=net, restart=16,
+                                                     rhs_block=8), 8)
+    ctx.profile_enable(False)
+    nl, ms, fl = ctx.profile_get(d.K_NN)
+    tf = fl / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    out["mixed_batched_learned_fgmres16"].update({
+        "train_pairs": ts.pairs, "train_steps": ts.steps, "train_loss_first": round(ts.first_loss, 4),
+        "train_loss_final": round(ts.final_loss, 4), "train_seconds": round(train_s, 2)})
+    nn_roof = {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_nn_layer (network layers, BF16 matrix cores)",
+               "launches": nl, "avg_launch_ms": round(ms / max(nl, 1), 4)}
+    return out, nn_roof
+
+
 def cpu_baseline(pre, seconds_budget=30.0):
     """The oracle on the host cores: one full-operator CGNR solve of the same
     workload to 1e-10 plus its projection at the source timeslice."""
@@ -157,7 +213,6 @@ def main():
         step(k)
         print("warmup step %d done" % k, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    tag = {d.BF16: d.K_STENCIL_BF16, d.F32: d.K_STENCIL_F32}[inner]
     t0 = time.perf_counter()
     rhs = 0
     solves = 0
@@ -181,23 +236,33 @@ def main():
     ctx.profile_enable(True)
     step(args.warmup + args.steps)
     ctx.profile_enable(False)
-    nl, ms, by = ctx.profile_get(tag)
-    print("profiled step done: %d stencil launches" % nl, file=sys.stderr, flush=True)
+    # dominant kernel: the inner-precision stencil family with the most launches
+    # (the even-odd half-lattice stencil when every extent is even)
+    fams = {"k_dslash<%s>" % io: fam for io, fam in (("IOBF", d.K_STENCIL_BF16), ("IO32", d.K_STENCIL_F32))}
+    fams.update({"k_dslash_eo<%s>" % io: fam for io, fam in (("IOBF", d.K_STENCIL_EO_BF16),
+                                                              ("IO32", d.K_STENCIL_EO_F32))})
+    io = "IOBF" if inner == d.BF16 else "IO32"
+    cands = [t for t in fams if io in t]
+    stats = {t: ctx.profile_get(fams[t]) for t in cands}
+    kernel_tag = max(stats, key=lambda t: stats[t][0])
+    nl, ms, by = stats[kernel_tag]
+    sites = ctx.V // 2 if "_eo" in kernel_tag else ctx.V
+    print("profiled step done: %d launches of %s" % (nl, kernel_tag), file=sys.stderr, flush=True)
     avg_ms = ms / max(nl, 1)
     gbps = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     blk = args.rhs_block or tuned
-    tflops = FLOP_PER_SITE_RHS * ctx.V * blk / (avg_ms / 1e3) / 1e12 if avg_ms > 0 else 0.0
-    kernel_tag = "k_dslash<%s>" % ("IOBF" if inner == d.BF16 else "IO32")
+    tflops = FLOP_PER_SITE_RHS * sites * blk / (avg_ms / 1e3) / 1e12 if avg_ms > 0 else 0.0
     # The multi-RHS stencil is bound by vector-ALU issue, not HBM: report the ALU
     # roofline, with the algorithmic HBM rate (the metric's GB/s) beside it.
     roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
             "unit": "TFLOP/s", "frac": round(tflops / VALU_FP32_PEAK_TFLOPS, 4),
             "traffic": load_traffic("%s/n%d" % (kernel_tag, blk)),
             "hbm_gbps": round(gbps, 1), "hbm_peak_gbps": HBM_PEAK_GBPS, "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
-            "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, %d RHS per launch)" % blk,
+            "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, %d RHS per launch, %d sites)" % (blk, sites),
             "avg_launch_ms": round(avg_ms, 5), "launches_timed": nl,
             "alg_bytes_per_launch": round(by / max(nl, 1)),
-            "flop_per_launch": FLOP_PER_SITE_RHS * ctx.V * blk}
+            "flop_per_launch": FLOP_PER_SITE_RHS * sites * blk}
+    comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
     out = {
         "metric": METRIC, "value": round(rhs / dt, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
@@ -211,6 +276,8 @@ def main():
                    "outer": "f64", "logical_rhs_per_step": rhs // max(args.steps, 1),
                    "solves_per_step": solves // max(args.steps, 1)},
         "roofline": roof,
+        "solver_comparison": comparison,
+        "nn_roofline": nn_roof,
         "worst_true_rel_residual": worst,
         "inner_iterations": iters,
         "setup_s": round(setup_s, 3),

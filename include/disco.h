@@ -152,7 +152,13 @@ enum {
                            * (captured on a private stream, launched on the context stream;
                            * skipped while profiling is enabled); 0: eager launches */
     DISCO_OPT_STAGE = 2   /* LDS staging of links/clover in FP32/BF16 stencils: -1 auto
-                           * (16 or more right-hand sides per launch), 0 off, 1 on */
+                           * (16 or more right-hand sides per launch), 0 off, 1 on */,
+    DISCO_OPT_EO = 3      /* 1 (default): inner BiCGStab solves of BICGSTAB_DC run on the
+                           * even-odd Schur complement M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe
+                           * (D = A - kappa H; half-lattice vectors) when every extent is even,
+                           * with the source A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o) and the odd
+                           * sites reconstructed as A_oo^-1 (r_o + kappa H_oe e_e); the FP64
+                           * outer residual stays that of the full operator.  0: full operator */
 };
 int disco_set_option(disco_ctx* ctx, int option, int value);
 
@@ -296,6 +302,10 @@ int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int
  * keeps the transporters of the gauge field current at creation. */
 int disco_net_create(disco_ctx* ctx, int channels, unsigned long long seed, disco_net** out);
 int disco_net_destroy(disco_net* net);
+/* Re-tabulate the transporters from the context's current gauge field (after
+ * disco_gauge_set with another configuration; the weights and the optimiser
+ * state are kept, so training can continue over several ensembles). */
+int disco_net_refresh(disco_net* net);
 /* number of floats of the packed weights */
 long long disco_net_weights_count(const disco_net* net);
 int disco_net_set_weights(disco_net* net, const float* w, int where);
@@ -338,7 +348,9 @@ int disco_net_train(disco_net* net, const disco_train_params* p, disco_train_sta
  * term counted once per site); 10, 11, 12 = the same split by storage
  * precision (FP64, FP32, BF16); 1 = FP64 matrix-core contraction
  * (perambulator, eigensolver Gram matrices): bytes holds the flop count;
- * 2 = network layers (BF16 matrix cores): bytes holds the flop count. */
+ * 2 = network layers (BF16 matrix cores): bytes holds the flop count;
+ * 13, 14, 15 = even-odd (half-lattice) stencil launches by storage precision:
+ * bytes = algorithmic bytes (spinors once, all links of the visited sites, A^-1). */
 enum { DISCO_KERNEL_STENCIL = 0, DISCO_KERNEL_MFMA64 = 1, DISCO_KERNEL_NN = 2 };
 int disco_profile_enable(disco_ctx* ctx, int on);
 /* Time only every `stride`-th profiled launch of each family (default 1). */

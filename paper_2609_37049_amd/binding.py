@@ -24,7 +24,8 @@ K_STENCIL = 0
 K_NN = 2
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
 K_MFMA = 1
-OPT_GRAPHS, OPT_STAGE = 1, 2
+OPT_GRAPHS, OPT_STAGE, OPT_EO = 1, 2, 3
+K_STENCIL_EO_F64, K_STENCIL_EO_F32, K_STENCIL_EO_BF16 = 13, 14, 15
 
 
 class DiscoError(RuntimeError):
@@ -97,6 +98,7 @@ _SIGS.update({
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
     "disco_net_create": ([P, I, ctypes.c_ulonglong, P], I),
     "disco_net_destroy": ([P], I),
+    "disco_net_refresh": ([P], I),
     "disco_net_weights_count": ([P], LL),
     "disco_net_set_weights": ([P, P, I], I),
     "disco_net_get_weights": ([P, P, I], I),
@@ -187,6 +189,10 @@ class Net:
             self.close()
         except Exception:
             pass
+
+    def refresh(self):
+        """Re-tabulate the transporters after the context's gauge field changed."""
+        self.ctx._chk(lib().disco_net_refresh(self.h))
 
     def get_weights(self) -> np.ndarray:
         w = np.empty(self.nw, dtype=np.float32)

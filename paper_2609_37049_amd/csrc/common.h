@@ -86,6 +86,9 @@ struct disco_ctx {
     // clover: FP64 [2][18][V] double2, FP32 [2][9][V] float4
     double2* A64 = nullptr;
     float4* A32 = nullptr;
+    // A^-1 in the same packed format (even-odd preconditioning)
+    double2* Ai64 = nullptr;
+    float4* Ai32 = nullptr;
     bool have_clover = false;
     double kappa = 0, csw = 0;
 
@@ -93,6 +96,9 @@ struct disco_ctx {
     // stencil visits sites (each XCD takes one contiguous range of g)
     int2* d_trav = nullptr;
     int trav_kind = 0;
+    // the same order restricted to the sites of one parity (x+y+z+t even / odd);
+    // a site s of either parity has index s/2 in a half-lattice vector
+    int2* d_trav_eo[2] = {nullptr, nullptr};
 
     // named, grow-only device workspaces
     std::map<std::string, std::pair<void*, size_t>> ws;
@@ -100,6 +106,7 @@ struct disco_ctx {
     // options
     int opt_graphs = 1;   // capture inner Krylov iteration chunks as HIP graphs
     int opt_stage = -1;   // LDS staging of links/clover in the stencil: -1 auto, 0 off, 1 on
+    int opt_eo = 1;       // even-odd (Schur) preconditioned inner solves when every extent is even
     // graph cache: key -> executable graph; private capture stream
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;
@@ -245,9 +252,14 @@ struct StencilCall {
     const uint8_t* mask;  // null = full operator
     double2* part;        // partial sums [r][nq][nsb]
     int epi;
+    // even-odd mode: parity of the sites written (0 even, 1 odd), -1 = full operator;
+    // out = ca*aux + A^-1 (cg*aux + cb*H in), in and aux/aux2/out half-lattice vectors
+    int eo_target = -1;
+    double ca = 0, cg = 0, cb = 0;
 };
 int nq_of(int epi);
-int stencil_nsb(disco_ctx* ctx, int n);   // partial-sum slots per (rhs, quantity)
+int stencil_nsb(disco_ctx* ctx, int n, bool eo = false);   // partial-sum slots per (rhs, quantity)
+bool eo_supported(const disco_ctx* ctx);
 int stencil_spb(int n);                    // sites per stencil block
 void build_traversal(disco_ctx* ctx);
 void stencil_launch(disco_ctx* ctx, const StencilCall& c);

@@ -233,6 +233,70 @@ __global__ void k_clover(const double2* __restrict__ U, Geo g, long V, double ck
     }
 }
 
+// A(x)^-1 per site and chiral block (Gauss-Jordan with partial pivoting in
+// FP64), stored in the packed format of A (the inverse of a hermitian matrix is
+// hermitian: the upper triangle is the mean of (i,j) and conj(j,i)).
+__global__ void k_clover_inv(const double2* __restrict__ A64, long V, double2* __restrict__ Ai64,
+                             float4* __restrict__ Ai32) {
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    for (int blk = 0; blk < 2; blk++) {
+        double f[36];
+        for (int q = 0; q < 18; q++) {
+            double2 v = A64[((long)blk * 18 + q) * V + s];
+            f[2 * q] = v.x;
+            f[2 * q + 1] = v.y;
+        }
+        cd M[6][12];
+        for (int i = 0; i < 6; i++)
+            for (int j = 0; j < 12; j++) M[i][j] = mk(j == i + 6 ? 1.0 : 0.0, 0.0);
+        for (int i = 0; i < 6; i++) M[i][i] = mk(f[i], 0.0);
+        int m = 0;
+        for (int i = 0; i < 6; i++)
+            for (int j = i + 1; j < 6; j++, m++) {
+                M[i][j] = mk(f[6 + 2 * m], f[7 + 2 * m]);
+                M[j][i] = mk(f[6 + 2 * m], -f[7 + 2 * m]);
+            }
+        for (int c = 0; c < 6; c++) {
+            int pr = c;
+            double best = nrm(M[c][c]);
+            for (int r = c + 1; r < 6; r++)
+                if (nrm(M[r][c]) > best) {
+                    best = nrm(M[r][c]);
+                    pr = r;
+                }
+            if (pr != c)
+                for (int j = 0; j < 12; j++) {
+                    cd t = M[c][j];
+                    M[c][j] = M[pr][j];
+                    M[pr][j] = t;
+                }
+            const cd piv = M[c][c];
+            const double dn = nrm(piv);
+            const cd inv = mk(piv.re / dn, -piv.im / dn);
+            for (int j = 0; j < 12; j++) M[c][j] = inv * M[c][j];
+            for (int r = 0; r < 6; r++) {
+                if (r == c) continue;
+                const cd fac = M[r][c];
+                for (int j = 0; j < 12; j++) M[r][j] = M[r][j] - fac * M[c][j];
+            }
+        }
+        double g[36];
+        for (int i = 0; i < 6; i++) g[i] = M[i][i + 6].re;
+        m = 0;
+        for (int i = 0; i < 6; i++)
+            for (int j = i + 1; j < 6; j++, m++) {
+                const cd a = M[i][j + 6], b = M[j][i + 6];
+                g[6 + 2 * m] = 0.5 * (a.re + b.re);
+                g[7 + 2 * m] = 0.5 * (a.im - b.im);
+            }
+        for (int q = 0; q < 18; q++) Ai64[((long)blk * 18 + q) * V + s] = make_double2(g[2 * q], g[2 * q + 1]);
+        for (int q = 0; q < 9; q++)
+            Ai32[((long)blk * 9 + q) * V + s] =
+                make_float4((float)g[4 * q], (float)g[4 * q + 1], (float)g[4 * q + 2], (float)g[4 * q + 3]);
+    }
+}
+
 __global__ void k_clover_expand(const double2* __restrict__ A64, long V, double2* __restrict__ out) {
     long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
@@ -298,8 +362,12 @@ int disco_destroy(disco_ctx* ctx) {
     hipFree(ctx->U32);
     hipFree(ctx->Usm);
     hipFree(ctx->A64);
+    hipFree(ctx->Ai64);
+    hipFree(ctx->Ai32);
     hipFree(ctx->A32);
     hipFree(ctx->d_trav);
+    hipFree(ctx->d_trav_eo[0]);
+    hipFree(ctx->d_trav_eo[1]);
     for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     for (auto& r : ctx->prof) {
@@ -363,6 +431,8 @@ int disco_clover_setup(disco_ctx* ctx, double kappa, double csw) {
         if (!ctx->A64) {
             HIPCHK(hipMalloc(&ctx->A64, (size_t)V * 36 * sizeof(double2) / 1));
             HIPCHK(hipMalloc(&ctx->A32, (size_t)V * 18 * sizeof(float4)));
+            HIPCHK(hipMalloc(&ctx->Ai64, (size_t)V * 36 * sizeof(double2)));
+            HIPCHK(hipMalloc(&ctx->Ai32, (size_t)V * 18 * sizeof(float4)));
         }
         Geo g;
         long st = 1;
@@ -372,6 +442,7 @@ int disco_clover_setup(disco_ctx* ctx, double kappa, double csw) {
             st *= ctx->dims[m];
         }
         k_clover<<<(int)((V + 127) / 128), 128, 0, ctx->stream>>>(ctx->U64, g, V, csw * kappa, ctx->A64, ctx->A32);
+        k_clover_inv<<<(int)((V + 127) / 128), 128, 0, ctx->stream>>>(ctx->A64, V, ctx->Ai64, ctx->Ai32);
         HIPCHK(hipGetLastError());
         ctx->kappa = kappa;
         ctx->csw = csw;
@@ -446,6 +517,9 @@ int disco_set_option(disco_ctx* ctx, int option, int value) {
         } else if (option == DISCO_OPT_STAGE) {
             REQUIRE(value >= -1 && value <= 1, DISCO_EINVAL, "stage option is -1, 0 or 1");
             ctx->opt_stage = value;
+        } else if (option == DISCO_OPT_EO) {
+            REQUIRE(value == 0 || value == 1, DISCO_EINVAL, "even-odd option is 0 or 1");
+            ctx->opt_eo = value;
         } else {
             disco_throw(DISCO_EINVAL, "unknown option %d", option);
         }

@@ -10,8 +10,9 @@
 // covariant.  Offsets are numbered k = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1).
 //
 // GPU design (gfx950):
-//  * transporters of all 81 offsets are tabulated once per gauge field in FP32
-//    ([81][V][9] complex, 5.8 KB per site);
+//  * transporters of all 81 offsets are tabulated once per gauge field as
+//    BF16 pairs ([81][V][9] x {(Re, -Im), (Im, Re)}, 5.8 KB per site), so a
+//    complex multiply-add on packed BF16 activations is two v_dot2_f32_bf16;
 //  * activations are BF16 complex, [rhs][V][C][12] (site-major, so one
 //    neighbour gather reads 48 contiguous bytes per channel);
 //  * one layer is one kernel per tile of 64 sites (a 4x4x2x2 block): for each
@@ -50,6 +51,32 @@ __device__ __forceinline__ uint32_t pk2(float a, float b) {
 }
 __device__ __forceinline__ cx<float> unpk(uint32_t w) {
     return mk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf2v, a), __builtin_bit_cast(bf2v, b), c, false);
+}
+// o[s*3+a] = sum_b M[a][b] psi[s*3+b] on packed BF16 (re low, im high), M = T or
+// T^+ (ADJ); T[k] = {(Tr, -Ti), (Ti, Tr)} of entry k = row*3 + col.  Conjugating
+// flips the sign of Ti: (Tr, Ti) and (-Ti, Tr) by one XOR of a sign bit each.
+template <bool ADJ>
+__device__ __forceinline__ void transport_bf(const uint2 (&T)[9], const uint32_t (&psi)[12], uint32_t (&o)[12]) {
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const uint2 t = T[ADJ ? b * 3 + a : a * 3 + b];
+                const uint32_t wa = ADJ ? (t.x ^ 0x80000000u) : t.x;
+                const uint32_t wb = ADJ ? (t.y ^ 0x00008000u) : t.y;
+                re = dot2(wa, psi[s * 3 + b], re);
+                im = dot2(wb, psi[s * 3 + b], im);
+            }
+            o[s * 3 + a] = pk2(re, im);
+        }
 }
 
 struct TileGeo {
@@ -91,8 +118,9 @@ __device__ __forceinline__ int shifted_site(const TileGeo& g, const int c[4], in
 
 // ------------------------------------------------------------------ transporters
 // T[d][x]: product of the links along the axis-ordered path from x to x + d,
-// computed in FP64 from the links, stored FP32.  One thread per (site, offset).
-__global__ void k_nn_ttab(const double2* __restrict__ U, long V, TileGeo g, float2* __restrict__ ttab) {
+// computed in FP64 from the links, stored as BF16 pairs (round to nearest even).
+// One thread per (site, offset).
+__global__ void k_nn_ttab(const double2* __restrict__ U, long V, TileGeo g, uint2* __restrict__ ttab) {
     const long tot = V * kOff;
     for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
         const int d = (int)(j / V);
@@ -139,7 +167,10 @@ __global__ void k_nn_ttab(const double2* __restrict__ U, long V, TileGeo g, floa
                 }
             for (int k = 0; k < 9; k++) M[k] = P[k];
         }
-        for (int k = 0; k < 9; k++) ttab[((long)d * V + s) * 9 + k] = make_float2((float)M[k].re, (float)M[k].im);
+        for (int k = 0; k < 9; k++) {
+            const float tr = (float)M[k].re, ti = (float)M[k].im;
+            ttab[((long)d * V + s) * 9 + k] = make_uint2(pk2(tr, -ti), pk2(ti, tr));
+        }
     }
 }
 
@@ -192,7 +223,7 @@ static inline long frag_elems(int ci, int co) { return (long)nbatch_of(ci) * 4 *
 struct LayerArgs {
     const uint32_t* in;   // [n][V][CI][12] bf16 (re, im) pairs
     void* out;            // [n][V][CO][12] bf16 pairs (uint32) or float2
-    const float2* ttab;   // [81][V][9]
+    const uint2* ttab;    // [81][V][9] BF16 pairs
     const uint4* frag;
     long V;
     int nlogical;
@@ -229,71 +260,79 @@ __global__ __launch_bounds__(256) void k_nn_layer(const LayerArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; c++) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int batch = 0; batch < NBATCH; batch++) {
+    // CI = 16: the four channels of a thread share the offset; the next offset's
+    // transporter and neighbour spinors are fetched while the matrix cores work
+    uint2 Tn[CI == 16 ? 9 : 1];
+    uint32_t rn[CI == 16 ? 4 : 1][12];
+    auto fetch16 = [&](int d) {
+        const int ys = shifted_site(a.g, cs, d, ADJ ? -1 : 1);
+        const uint2* tp = a.ttab + ((size_t)d * a.V + (ADJ ? ys : site)) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; k++) Tn[k] = tp[k];
 #pragma unroll
         for (int pp = 0; pp < 4; pp++) {
-            const int p = q * 4 + pp;
-            const int dl = p / CI, i = p % CI;
-            const int d = batch * NB + dl;
-            uint4 wr[3] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-            if (d < kOff) {
-                const int ys = shifted_site(a.g, cs, d, ADJ ? -1 : 1);
-                const int ts = ADJ ? ys : site;
-                const float2* tp = a.ttab + ((size_t)d * a.V + ts) * 9;
-                cx<float> M[9];
+            const uint4* ip = (const uint4*)(inr + ((size_t)ys * CI + q * 4 + pp) * 12);
 #pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    float2 t = tp[k];
-                    M[k] = mk(t.x, t.y);
-                }
-                if (ADJ) {
-                    cx<float> Mt[9];
-#pragma unroll
-                    for (int x = 0; x < 3; x++)
-#pragma unroll
-                        for (int y = 0; y < 3; y++) Mt[x * 3 + y] = cj(M[y * 3 + x]);
-#pragma unroll
-                    for (int k = 0; k < 9; k++) M[k] = Mt[k];
-                }
-                const uint4* ip = (const uint4*)(inr + ((size_t)ys * CI + i) * 12);
-                uint32_t raw[12];
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    uint4 v = ip[k];
-                    raw[4 * k] = v.x;
-                    raw[4 * k + 1] = v.y;
-                    raw[4 * k + 2] = v.z;
-                    raw[4 * k + 3] = v.w;
-                }
-                uint32_t o[4][3];
-#pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    const cx<float> p0 = unpk(raw[s * 3]), p1 = unpk(raw[s * 3 + 1]), p2 = unpk(raw[s * 3 + 2]);
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        float re = M[c * 3].re * p0.re;
-                        re = fmaf(-M[c * 3].im, p0.im, re);
-                        re = fmaf(M[c * 3 + 1].re, p1.re, re);
-                        re = fmaf(-M[c * 3 + 1].im, p1.im, re);
-                        re = fmaf(M[c * 3 + 2].re, p2.re, re);
-                        re = fmaf(-M[c * 3 + 2].im, p2.im, re);
-                        float im = M[c * 3].re * p0.im;
-                        im = fmaf(M[c * 3].im, p0.re, im);
-                        im = fmaf(M[c * 3 + 1].re, p1.im, im);
-                        im = fmaf(M[c * 3 + 1].im, p1.re, im);
-                        im = fmaf(M[c * 3 + 2].re, p2.im, im);
-                        im = fmaf(M[c * 3 + 2].im, p2.re, im);
-                        o[s][c] = pk2(re, im);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < 3; c++) wr[c] = make_uint4(o[0][c], o[1][c], o[2][c], o[3][c]);
+            for (int k = 0; k < 3; k++) {
+                const uint4 v = ip[k];
+                rn[pp][4 * k] = v.x;
+                rn[pp][4 * k + 1] = v.y;
+                rn[pp][4 * k + 2] = v.z;
+                rn[pp][4 * k + 3] = v.w;
             }
-            const int kk = (dl * CI + i) * 8;
+        }
+    };
+    if constexpr (CI == 16) fetch16(0);
+
+    for (int batch = 0; batch < NBATCH; batch++) {
+        if constexpr (CI == 16) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) *(uint4*)&lds[(sl * 3 + c) * kLdk + kk] = wr[c];
+            for (int pp = 0; pp < 4; pp++) {
+                uint32_t o[12];
+                transport_bf<ADJ>(Tn, rn[pp], o);
+                const int kk = (q * 4 + pp) * 8;
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    *(uint4*)&lds[(sl * 3 + c) * kLdk + kk] = make_uint4(o[c], o[3 + c], o[6 + c], o[9 + c]);
+            }
+        } else {
+#pragma unroll
+            for (int pp = 0; pp < 4; pp++) {
+                const int p = q * 4 + pp;
+                const int dl = p / CI, i = p % CI;
+                const int d = batch * NB + dl;
+                uint32_t o[12];
+                if (d < kOff) {
+                    const int ys = shifted_site(a.g, cs, d, ADJ ? -1 : 1);
+                    const uint2* tp = a.ttab + ((size_t)d * a.V + (ADJ ? ys : site)) * 9;
+                    uint2 T[9];
+#pragma unroll
+                    for (int k = 0; k < 9; k++) T[k] = tp[k];
+                    const uint4* ip = (const uint4*)(inr + ((size_t)ys * CI + i) * 12);
+                    uint32_t raw[12];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const uint4 v = ip[k];
+                        raw[4 * k] = v.x;
+                        raw[4 * k + 1] = v.y;
+                        raw[4 * k + 2] = v.z;
+                        raw[4 * k + 3] = v.w;
+                    }
+                    transport_bf<ADJ>(T, raw, o);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; k++) o[k] = 0u;
+                }
+                const int kk = (dl * CI + i) * 8;
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    *(uint4*)&lds[(sl * 3 + c) * kLdk + kk] = make_uint4(o[c], o[3 + c], o[6 + c], o[9 + c]);
+            }
         }
         __syncthreads();
+        if constexpr (CI == 16) {
+            if (batch + 1 < NBATCH) fetch16(batch + 1);
+        }
         const uint4* fb = a.frag + (size_t)batch * 4 * RT * 64;
 #pragma unroll
         for (int ks = 0; ks < 4; ks++) {
@@ -343,7 +382,7 @@ __global__ __launch_bounds__(256) void k_nn_layer(const LayerArgs a) {
 struct DwArgs {
     const uint32_t* act;  // layer input [n][V][CI][12]
     const uint32_t* g;    // gradient at the layer output [n][V][CO][12]
-    const float2* ttab;
+    const uint2* ttab;
     float* part;          // [nbatch][nchunk][MOP][128]
     long V;
     int n, nchunk, nlogical;
@@ -386,7 +425,7 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
         __syncthreads();
         // B: transported inputs phi, rows (d_local, i, t, b), K (colour, site)
         {
-            float vr[4][4][3], vi[4][4][3];  // [site u][spin][colour]
+            uint32_t ph[4][12];  // [site u][spin*3 + colour], packed BF16
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 int cs[4];
@@ -394,38 +433,24 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
                 if (d < kOff) {
                     const int s0 = site_of(a.g_, cs);
                     const int ys = shifted_site(a.g_, cs, d, 1);
-                    const float2* tp = a.ttab + ((size_t)d * a.V + s0) * 9;
-                    cx<float> M[9];
+                    const uint2* tp = a.ttab + ((size_t)d * a.V + s0) * 9;
+                    uint2 T[9];
 #pragma unroll
-                    for (int k = 0; k < 9; k++) {
-                        float2 t = tp[k];
-                        M[k] = mk(t.x, t.y);
-                    }
+                    for (int k = 0; k < 9; k++) T[k] = tp[k];
                     const uint4* ip = (const uint4*)(a.act + (((size_t)rhs * a.V + ys) * CI + ich) * 12);
                     uint32_t raw[12];
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        uint4 v = ip[k];
+                        const uint4 v = ip[k];
                         raw[4 * k] = v.x;
                         raw[4 * k + 1] = v.y;
                         raw[4 * k + 2] = v.z;
                         raw[4 * k + 3] = v.w;
                     }
-#pragma unroll
-                    for (int s = 0; s < 4; s++) {
-                        const cx<float> p0 = unpk(raw[s * 3]), p1 = unpk(raw[s * 3 + 1]), p2 = unpk(raw[s * 3 + 2]);
-#pragma unroll
-                        for (int c = 0; c < 3; c++) {
-                            const cx<float> v = M[c * 3] * p0 + M[c * 3 + 1] * p1 + M[c * 3 + 2] * p2;
-                            vr[u][s][c] = v.re;
-                            vi[u][s][c] = v.im;
-                        }
-                    }
+                    transport_bf<false>(T, raw, ph[u]);
                 } else {
 #pragma unroll
-                    for (int s = 0; s < 4; s++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++) vr[u][s][c] = vi[u][s][c] = 0.f;
+                    for (int k = 0; k < 12; k++) ph[u][k] = 0u;
                 }
             }
 #pragma unroll
@@ -433,10 +458,12 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     const int k = c * 64 + sg * 4;
+                    const int e = s * 3 + c;
                     *(uint2*)&sB[(p * 8 + s * 2) * kLdw + k] =
-                        make_uint2(pk2(vr[0][s][c], vr[1][s][c]), pk2(vr[2][s][c], vr[3][s][c]));
+                        make_uint2((ph[0][e] & 0xffffu) | (ph[1][e] << 16), (ph[2][e] & 0xffffu) | (ph[3][e] << 16));
                     *(uint2*)&sB[(p * 8 + s * 2 + 1) * kLdw + k] =
-                        make_uint2(pk2(vi[0][s][c], vi[1][s][c]), pk2(vi[2][s][c], vi[3][s][c]));
+                        make_uint2((ph[0][e] >> 16) | (ph[1][e] & 0xffff0000u),
+                                   (ph[2][e] >> 16) | (ph[3][e] & 0xffff0000u));
                 }
         }
         // A: gradient rows (o, s, a), K (colour, site)
@@ -684,7 +711,7 @@ struct disco_net {
     float* am = nullptr;           // Adam moments
     float* av = nullptr;
     int adam_t = 0;
-    float2* ttab = nullptr;
+    uint2* ttab = nullptr;
     uint16_t* ffwd[3] = {nullptr, nullptr, nullptr};
     uint16_t* fadj[3] = {nullptr, nullptr, nullptr};
     bool frags_ok = false;
@@ -849,7 +876,7 @@ extern "C" int disco_net_create(disco_ctx* ctx, int channels, unsigned long long
         HIPCHK(hipMalloc(&net->gw, sizeof(float) * net->nw));
         HIPCHK(hipMalloc(&net->am, sizeof(float) * net->nw));
         HIPCHK(hipMalloc(&net->av, sizeof(float) * net->nw));
-        HIPCHK(hipMalloc(&net->ttab, sizeof(float2) * 9 * (size_t)kOff * ctx->V));
+        HIPCHK(hipMalloc(&net->ttab, sizeof(uint2) * 9 * (size_t)kOff * ctx->V));
         for (int l = 0; l < 3; l++) {
             HIPCHK(hipMalloc(&net->ffwd[l], sizeof(uint16_t) * frag_elems(net->lci[l], net->lco[l])));
             HIPCHK(hipMalloc(&net->fadj[l], sizeof(uint16_t) * frag_elems(net->lco[l], net->lci[l])));
@@ -901,6 +928,16 @@ extern "C" int disco_net_destroy(disco_net* net) {
 }
 
 extern "C" long long disco_net_weights_count(const disco_net* net) { return net ? (long long)net->nw : -1; }
+
+extern "C" int disco_net_refresh(disco_net* net) {
+    if (!net) return DISCO_EINVAL;
+    return guarded(net->ctx, [&] {
+        REQUIRE(net->ctx->have_gauge, DISCO_ESTATE, "no gauge field");
+        activate(net->ctx);
+        net_build_ttab(net);
+        HIPCHK(hipStreamSynchronize(net->ctx->stream));
+    });
+}
 
 extern "C" int disco_net_set_weights(disco_net* net, const float* w, int where) {
     if (!net || !w) return DISCO_EINVAL;

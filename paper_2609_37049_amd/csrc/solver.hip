@@ -499,11 +499,37 @@ static void cgnr_run(Work& w, const double2* rhs, double2* e, const uint8_t* mas
     *iters += it;
 }
 
-// inner BiCGStab on D e = rin (normalised defect) in storage IO
+// Operator of an inner Krylov solve: the full (or domain-restricted) D on
+// whole-lattice vectors, or the even-odd Schur complement
+//   M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe
+// on even half-lattice vectors (two even-odd stencil launches, the second
+// carrying the reduction epilogue).
+struct InnerOp {
+    bool eo = false;
+    long Vv = 0;   // sites of the vectors
+    int nsb = 0;   // partial-sum slots of the launch with the epilogue
+};
+
+static void op_apply(Work& w, const InnerOp& op, int prec, const void* in, void* out, const void* aux2,
+                     const uint8_t* mask, int epi, void* tmp) {
+    if (!op.eo) {
+        stencil(w, prec, 0, in, out, nullptr, aux2, mask, epi);
+        return;
+    }
+    const double k = w.ctx->kappa;
+    disco::StencilCall c1{prec, 0, w.n, in, tmp, nullptr, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 0.0, 1.0};
+    disco::stencil_launch(w.ctx, c1);
+    disco::StencilCall c2{prec, 0, w.n, tmp, out, in, aux2, mask, w.part, epi, 0, 1.0, 0.0, -k * k};
+    disco::stencil_launch(w.ctx, c2);
+}
+
+// inner BiCGStab on op e = rin (normalised defect) in storage IO
 template <class IO>
-static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol, int max_iter,
-                    int check_every) {
+static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void* e, const uint8_t* mask,
+                    double inner_tol, int max_iter, int check_every) {
     disco_ctx* ctx = w.ctx;
+    const long Vfull = w.V;
+    w.V = op.Vv;  // vector helpers below work on the operator's vectors
     VecGeo g = vgeo(w.V, prec, w.n);
     size_t nb = disco::native_bytes(ctx, prec, w.n);
     void* r = ws_get(ctx, "bi_r", nb);
@@ -512,6 +538,7 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
     void* v = ws_get(ctx, "bi_v", nb);
     void* s = ws_get(ctx, "bi_s", nb);
     void* t = ws_get(ctx, "bi_t", nb);
+    void* tmp = op.eo ? ws_get(ctx, "bi_eotmp", nb / 2) : nullptr;
     k_zero<IO><<<1024, 256, 0, ctx->stream>>>(e, g.total);
     copy_scale<IO, IO>(w, rin, r, 0);
     copy_scale<IO, IO>(w, rin, rh, 0);
@@ -519,13 +546,13 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
     norm2<IO>(w, r, g);
     k_sc_bicg_init<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc);
     const double tol2 = inner_tol * inner_tol;
-    // one BiCGStab iteration: 2 stencils with fused reductions, 3 vector updates, 3 scalar steps
+    // one BiCGStab iteration: 2 operator applications with fused reductions, 3 vector updates, 3 scalar steps
     auto iteration = [&]() {
-        stencil(w, prec, 0, p, v, nullptr, rh, mask, disco::EPI_DOTAUX);
-        k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+        op_apply(w, op, prec, p, v, rh, mask, disco::EPI_DOTAUX, tmp);
+        k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
-        stencil(w, prec, 0, s, t, nullptr, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN);
-        k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc);
+        op_apply(w, op, prec, s, t, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN, tmp);
+        k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_xr<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, r, rh, g, w.sc, w.part);
         k_sc_bicg_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
         hipLaunchKernelGGL(k_bicg_p<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, r, v, g, w.sc);
@@ -535,8 +562,8 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
     hipGraphExec_t exec = nullptr;
     if (ctx->opt_graphs && !ctx->prof_on && check_every > 1) {
         char key[512];
-        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g", prec, w.n, check_every, (void*)mask,
-                 r, rh, p, v, s, t, e, (void*)w.sc, (void*)w.part, tol2);
+        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g", prec, w.n, check_every,
+                 op.eo ? 1 : 0, (void*)mask, r, rh, p, v, s, t, e, tmp, (void*)w.sc, (void*)w.part, tol2);
         auto itg = ctx->graphs.find(key);
         if (itg != ctx->graphs.end()) {
             exec = itg->second;
@@ -555,6 +582,7 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
                 (void)hipStreamEndCapture(ctx->cap_stream, &dead);
                 if (dead) (void)hipGraphDestroy(dead);
                 ctx->stream = user;
+                w.V = Vfull;
                 throw;
             }
             hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
@@ -580,6 +608,108 @@ static int bicg_run(Work& w, int prec, const void* rin, void* e, const uint8_t* 
         for (auto& sc : w.h) any |= sc.active != 0;
         if (!any) break;
     }
+    w.V = Vfull;
+    return it;
+}
+
+// ---- even-odd helpers on native blocks (site s of parity p <-> index s/2 of half vector p)
+__device__ __forceinline__ int parity_of(long s, int Lx, int Ly, int Lz) {
+    const long x = s % Lx, r1 = s / Lx;
+    const long y = r1 % Ly, r2 = r1 / Ly;
+    const long z = r2 % Lz, t = r2 / Lz;
+    return (int)((x + y + z + t) & 1);
+}
+template <class IO>
+__global__ void k_eo_split(const void* __restrict__ full, void* __restrict__ he, void* __restrict__ ho, long V, int n,
+                           int Lx, int Ly, int Lz) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long st = j / n;
+        const int r = (int)(j - st * n);
+        cx<typename IO::T> p[12];
+        IO::load(full, V, n, r, (int)st, p);
+        IO::store(parity_of(st, Lx, Ly, Lz) ? ho : he, V / 2, n, r, (int)(st >> 1), p);
+    }
+}
+template <class IO>
+__global__ void k_eo_merge(const void* __restrict__ he, const void* __restrict__ ho, void* __restrict__ full, long V,
+                           int n, int Lx, int Ly, int Lz) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long st = j / n;
+        const int r = (int)(j - st * n);
+        cx<typename IO::T> p[12];
+        IO::load(parity_of(st, Lx, Ly, Lz) ? ho : he, V / 2, n, r, (int)(st >> 1), p);
+        IO::store(full, V, n, r, (int)st, p);
+    }
+}
+// out = A^-1 in on the half vector of parity par (site-local)
+template <class IO>
+__global__ void k_eo_clover_inv(const void* __restrict__ in, void* __restrict__ out, const void* __restrict__ Ai,
+                                long V, int n, int par, int Lx, int Ly, int Lz) {
+    typedef typename IO::T T;
+    const long Vh = V / 2;
+    const long tot = Vh * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long h = j / n;
+        const int r = (int)(j - h * n);
+        const long st = parity_of(2 * h, Lx, Ly, Lz) == par ? 2 * h : 2 * h + 1;
+        cx<T> p[12], o[12];
+        IO::load(in, Vh, n, r, (int)h, p);
+        T f[36];
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            IO::load_clover((const typename IO::CloverT*)Ai, V, b, (int)st, f);
+#pragma unroll
+            for (int i = 0; i < 6; i++) o[6 * b + i] = f[i] * p[6 * b + i];
+            int m = 0;
+#pragma unroll
+            for (int i = 0; i < 6; i++)
+#pragma unroll
+                for (int k = i + 1; k < 6; k++, m++) {
+                    const cx<T> a = mk(f[6 + 2 * m], f[7 + 2 * m]);
+                    o[6 * b + i] = o[6 * b + i] + a * p[6 * b + k];
+                    o[6 * b + k] = o[6 * b + k] + cj(a) * p[6 * b + i];
+                }
+        }
+        IO::store(out, Vh, n, r, (int)h, o);
+    }
+}
+
+// Inner solve D e = rin through the even-odd Schur complement:
+//   rhat = A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o),  M e_e = rhat (BiCGStab),
+//   e_o = A_oo^-1 (r_o + kappa H_oe e_e).
+template <class IO>
+static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol,
+                       int max_iter, int check_every) {
+    disco_ctx* ctx = w.ctx;
+    const long V = w.V;
+    const int n = w.n;
+    const size_t hb = disco::native_bytes(ctx, prec, n) / 2;
+    void* re = ws_get(ctx, "eo_re", hb);
+    void* ro = ws_get(ctx, "eo_ro", hb);
+    void* uo = ws_get(ctx, "eo_uo", hb);
+    void* rhat = ws_get(ctx, "eo_rhat", hb);
+    void* ee = ws_get(ctx, "eo_ee", hb);
+    void* eo = ws_get(ctx, "eo_eo", hb);
+    const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2];
+    const void* Ai = prec == DISCO_F64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32;
+    const int grid = site_grid(V, n);
+    const double k = ctx->kappa;
+    hipLaunchKernelGGL(k_eo_split<IO>, dim3(grid), dim3(256), 0, ctx->stream, rin, re, ro, V, n, Lx, Ly, Lz);
+    hipLaunchKernelGGL(k_eo_clover_inv<IO>, dim3(site_grid(V / 2, n)), dim3(256), 0, ctx->stream, ro, uo, Ai, V, n, 1,
+                       Lx, Ly, Lz);
+    disco::StencilCall cp{prec, 0, n, uo, rhat, re, nullptr, mask, nullptr, disco::EPI_NONE, 0, 0.0, 1.0, k};
+    disco::stencil_launch(ctx, cp);
+    InnerOp op;
+    op.eo = true;
+    op.Vv = V / 2;
+    op.nsb = disco::stencil_nsb(ctx, n, true);
+    const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every);
+    disco::StencilCall cr{prec, 0, n, ee, eo, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
+    disco::stencil_launch(ctx, cr);
+    hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, ee, eo, e, V, n, Lx, Ly, Lz);
+    HIPCHK(hipGetLastError());
     return it;
 }
 
@@ -638,6 +768,7 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
     const double itol = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-5);
     const int inner_cap = 2000;
     const bool trace = getenv("DISCO_TRACE") != nullptr;
+    const bool use_eo = ctx->opt_eo && disco::eo_supported(ctx);
     double last_worst = 1e300;
     int stall = 0;
     while (true) {
@@ -659,7 +790,14 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
         if (stall >= 3) break;  // no progress: leave it to the fallback
         outer++;
         copy_scale<IO64, IO>(w, r64, rin, 1);
-        iters += bicg_run<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+        if (use_eo) {
+            iters += bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+        } else {
+            InnerOp op;
+            op.Vv = w.V;
+            op.nsb = w.nsb;
+            iters += bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+        }
         dc_update<IO>(w, x64, e);
         outer_residual(w, b64, x64, r64, mask, tol2);
     }
@@ -1024,8 +1162,14 @@ extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inne
             // one untimed pass (graph capture, caches), then the timed one
             for (int rep = 0; rep < 2; rep++) {
                 HIPCHK(hipEventRecord(e0, ctx->stream));
-                if (inner_prec == DISCO_F32) bicg_run<IO32>(w, DISCO_F32, rin, e, mask, 0.0, iters, 10);
-                else bicg_run<IOBF>(w, DISCO_BF16, rin, e, mask, 0.0, iters, 10);
+                const bool eo = ctx->opt_eo && disco::eo_supported(ctx);
+                if (inner_prec == DISCO_F32) {
+                    if (eo) bicg_run_eo<IO32>(w, DISCO_F32, rin, e, mask, 0.0, iters, 10);
+                    else bicg_run<IO32>(w, InnerOp{false, w.V, w.nsb}, DISCO_F32, rin, e, mask, 0.0, iters, 10);
+                } else {
+                    if (eo) bicg_run_eo<IOBF>(w, DISCO_BF16, rin, e, mask, 0.0, iters, 10);
+                    else bicg_run<IOBF>(w, InnerOp{false, w.V, w.nsb}, DISCO_BF16, rin, e, mask, 0.0, iters, 10);
+                }
                 HIPCHK(hipEventRecord(e1, ctx->stream));
                 HIPCHK(hipEventSynchronize(e1));
             }

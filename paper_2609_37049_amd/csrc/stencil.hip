@@ -11,6 +11,15 @@
 // skipped and the clover term is kept (D_Lambda is D restricted to the fields
 // inside each domain).  The optional epilogue fuses the Krylov reductions
 // (deterministic per-block partial sums in FP64).
+//
+// Even-odd mode (EO): the launch visits the sites of one parity only, reads
+// the other parity's half-lattice vector (site s at index s/2), and forms
+//   out = ca * aux + A(x)^-1 (cg * aux + cb * H in)
+// with H the hopping sum (D = A - kappa H).  With the right coefficients this
+// is every piece of the Schur complement on the even sites,
+//   M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe,
+// its source A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o) and the reconstruction
+// x_o = A_oo^-1 (r_o + kappa H_oe x_e).
 #include <algorithm>
 #include <cstdlib>
 #include <string>
@@ -32,7 +41,11 @@ struct StencilArgs {
     const uint8_t* mask;
     const int2* trav;
     double2* part;
-    long V;
+    long V;        // lattice sites (stride of the link and clover planes)
+    long Vv;       // sites of the spinor vectors (V, or V/2 in even-odd mode)
+    int nsites;    // sites visited by the launch (entries of trav)
+    int eo_aux;    // even-odd mode: read aux at the site (ca, cg or DOTIN need it)
+    double ca, cg, cb;
     int L[4];
     long st[4];
     double ph[4];
@@ -157,12 +170,13 @@ __device__ __forceinline__ void clover6(const T f[36], const cx<T>* x, cx<T>* y)
 }
 
 // both hops in direction MU for right-hand side r at site s
-template <class IO, bool BUF, bool STAGE, int MU>
+template <class IO, bool BUF, bool STAGE, bool EO, int MU>
 __device__ __forceinline__ void hops(const StencilArgs& a, int s, const int* x, uint32_t m, int n, int r,
                                      const float2* sl, cx<typename IO::T> acc[12]) {
     typedef typename IO::T T;
     const typename IO::LinkT* U = (const typename IO::LinkT*)a.U;
     const long V = a.V;
+    const long Vv = a.Vv;
     const int L = a.L[MU];
     const int st = (int)a.st[MU];
     if (m & (1u << (2 * MU))) {
@@ -170,7 +184,7 @@ __device__ __forceinline__ void hops(const StencilArgs& a, int s, const int* x, 
         const bool wrap = x[MU] == L - 1;
         const int nb = wrap ? s - (L - 1) * st : s + st;
         cx<T> u[9], p[12], h[6], o[6];
-        IO::template loadv<BUF>(a.in, V, n, r, nb, p);
+        IO::template loadv<BUF>(a.in, Vv, n, r, EO ? (nb >> 1) : nb, p);
         if constexpr (STAGE) {
 #pragma unroll
             for (int k = 0; k < 9; k++) u[k] = mk((T)sl[(2 * MU) * 9 + k].x, (T)sl[(2 * MU) * 9 + k].y);
@@ -192,7 +206,7 @@ __device__ __forceinline__ void hops(const StencilArgs& a, int s, const int* x, 
         const bool wrap = x[MU] == 0;
         const int nb = wrap ? s + (L - 1) * st : s - st;
         cx<T> u[9], p[12], h[6], o[6];
-        IO::template loadv<BUF>(a.in, V, n, r, nb, p);
+        IO::template loadv<BUF>(a.in, Vv, n, r, EO ? (nb >> 1) : nb, p);
         if constexpr (STAGE) {
 #pragma unroll
             for (int k = 0; k < 9; k++) u[k] = mk((T)sl[(2 * MU + 1) * 9 + k].x, (T)sl[(2 * MU + 1) * 9 + k].y);
@@ -226,11 +240,12 @@ constexpr int kStageSites = 32;
 constexpr int kStageLinkBytes = 8 * 9 * 8;   // 8 links x 9 complex float
 constexpr int kStageCloverBytes = 18 * 16;   // 2 blocks x 9 float4
 
-template <class IO, int EPI, bool BUF, bool STAGE>
+template <class IO, int EPI, bool BUF, bool STAGE, bool EO>
 __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
     typedef typename IO::T T;
     constexpr int NQ = EpiCount<EPI>::nq;
     const int n = a.n;
+    const long Vv = a.Vv;
     const int spb = a.spb;  // sites per block; the block has spb*n active lanes
     const int sb = xcd_block(a.nsb);
     if (sb < 0) return;
@@ -255,7 +270,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
             const int i = e / 72, rem = e - i * 72, d = rem / 9, k = rem - d * 9;
             const int gi = g0 + i;
             float2 v = make_float2(0.f, 0.f);
-            if (gi < V) {
+            if (gi < a.nsites) {
                 const int2 tr = a.trav[gi];
                 const int mu = d >> 1;
                 int site = tr.x;
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
             const int i = e / 18, q = e - i * 18;
             const int gi = g0 + i;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gi < V) v = A[((long)(q / 9) * 9 + (q % 9)) * V + a.trav[gi].x];
+            if (gi < a.nsites) v = A[((long)(q / 9) * 9 + (q % 9)) * V + a.trav[gi].x];
             sA[i * 18 + q] = v;
         }
         __syncthreads();
@@ -279,7 +294,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         sa = sA + (t / n) * 18;
     }
 
-    if (t < nact && g < V) {
+    if (t < nact && g < a.nsites) {
         const int2 tr = a.trav[g];
         const int s = tr.x;
         const int x[4] = {tr.y & 0xff, (tr.y >> 8) & 0xff, (tr.y >> 16) & 0xff, (tr.y >> 24) & 0xff};
@@ -287,20 +302,34 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         cx<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = mk((T)0, (T)0);
-        hops<IO, BUF, STAGE, 0>(a, s, x, m, n, r, sl, acc);
-        hops<IO, BUF, STAGE, 1>(a, s, x, m, n, r, sl, acc);
-        hops<IO, BUF, STAGE, 2>(a, s, x, m, n, r, sl, acc);
-        hops<IO, BUF, STAGE, 3>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, EO, 0>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, EO, 1>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, EO, 2>(a, s, x, m, n, r, sl, acc);
+        hops<IO, BUF, STAGE, EO, 3>(a, s, x, m, n, r, sl, acc);
 
-        // site-local part: A(x) psi(x) - kappa * hops
+        // site-local part: A(x) psi(x) - kappa * hops, or in even-odd mode
+        // ca * aux + A(x)^-1 (cg * aux + cb * hops)
+        const int sv = EO ? (s >> 1) : s;
         cx<T> p[12], o[12];
-        IO::template loadv<BUF>(a.in, V, n, r, s, p);
         cx<T> pin[12];
-        if (EPI & disco::EPI_DOTIN) {
+        if constexpr (EO) {
+            if (a.eo_aux) {
+                IO::template loadv<BUF>(a.aux, Vv, n, r, sv, pin);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 12; k++) pin[k] = p[k];
+                for (int k = 0; k < 12; k++) pin[k] = mk((T)0, (T)0);
+            }
+            const T cg = (T)a.cg, cb = (T)a.cb;
+#pragma unroll
+            for (int k = 0; k < 12; k++) p[k] = mk(fma(cb, acc[k].re, cg * pin[k].re), fma(cb, acc[k].im, cg * pin[k].im));
+        } else {
+            IO::template loadv<BUF>(a.in, Vv, n, r, sv, p);
+            if (EPI & disco::EPI_DOTIN) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) pin[k] = p[k];
+            }
+            if (a.dagger) g5(p);
         }
-        if (a.dagger) g5(p);
         {
             T f[36];
             if constexpr (STAGE) {
@@ -323,21 +352,27 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
                 clover6(f, p + 6, o + 6);
             }
         }
-        const T kap = (T)a.kappa;
+        if constexpr (EO) {
+            const T ca = (T)a.ca;
 #pragma unroll
-        for (int k = 0; k < 12; k++) o[k] = mk(fma(-kap, acc[k].re, o[k].re), fma(-kap, acc[k].im, o[k].im));
-        if (a.dagger) g5(o);
-        if (EPI & disco::EPI_RESID) {
-            cx<T> b[12];
-            IO::template loadv<BUF>(a.aux, V, n, r, s, b);
+            for (int k = 0; k < 12; k++) o[k] = mk(fma(ca, pin[k].re, o[k].re), fma(ca, pin[k].im, o[k].im));
+        } else {
+            const T kap = (T)a.kappa;
 #pragma unroll
-            for (int k = 0; k < 12; k++) o[k] = b[k] - o[k];
+            for (int k = 0; k < 12; k++) o[k] = mk(fma(-kap, acc[k].re, o[k].re), fma(-kap, acc[k].im, o[k].im));
+            if (a.dagger) g5(o);
+            if (EPI & disco::EPI_RESID) {
+                cx<T> b[12];
+                IO::template loadv<BUF>(a.aux, Vv, n, r, sv, b);
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = b[k] - o[k];
+            }
         }
-        IO::store(a.out, V, n, r, s, o);
+        IO::store(a.out, Vv, n, r, sv, o);
         int q = 0;
         if (EPI & disco::EPI_DOTAUX) {
             cx<T> w[12];
-            IO::template loadv<BUF>(a.aux2, V, n, r, s, w);
+            IO::template loadv<BUF>(a.aux2, Vv, n, r, sv, w);
             double re = 0, im = 0;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
@@ -405,34 +440,43 @@ __global__ void k_from_native(const void* __restrict__ in, double2* __restrict__
     for (int k = 0; k < 12; k++) q[k] = make_double2((double)p[k].re, (double)p[k].im);
 }
 
-template <class IO, int EPI>
+template <class IO, int EPI, bool EO>
 void launch_one(disco_ctx* ctx, const StencilArgs& a) {
     const dim3 grid(xcd_grid(a.nsb)), block(kStencilBlock);
     const bool stage = sizeof(typename IO::T) == 4 && a.spb <= kStageSites && a.stage;
     if (stage) {
         const size_t shm = (size_t)a.spb * (kStageLinkBytes + kStageCloverBytes);
         if (a.in.buf)
-            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true>), grid, block, shm, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true, EO>), grid, block, shm, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_dslash<IO, EPI, false, true>), grid, block, shm, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, true, EO>), grid, block, shm, ctx->stream, a);
     } else {
         if (a.in.buf)
-            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false, EO>), grid, block, 0, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_dslash<IO, EPI, false, false>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, false, EO>), grid, block, 0, ctx->stream, a);
     }
 }
 
 template <class IO>
-void launch_epi(disco_ctx* ctx, const StencilArgs& a, int epi) {
+void launch_epi(disco_ctx* ctx, const StencilArgs& a, int epi, bool eo) {
     using namespace disco;
+    if (eo) {
+        switch (epi) {
+            case EPI_NONE: launch_one<IO, EPI_NONE, true>(ctx, a); break;
+            case EPI_DOTAUX: launch_one<IO, EPI_DOTAUX, true>(ctx, a); break;
+            case EPI_NORM | EPI_DOTIN: launch_one<IO, EPI_NORM | EPI_DOTIN, true>(ctx, a); break;
+            default: disco_throw(DISCO_EINVAL, "even-odd stencil epilogue %d not built", epi);
+        }
+        return;
+    }
     switch (epi) {
-        case EPI_NONE: launch_one<IO, EPI_NONE>(ctx, a); break;
-        case EPI_DOTAUX: launch_one<IO, EPI_DOTAUX>(ctx, a); break;
-        case EPI_NORM: launch_one<IO, EPI_NORM>(ctx, a); break;
-        case EPI_NORM | EPI_DOTIN: launch_one<IO, EPI_NORM | EPI_DOTIN>(ctx, a); break;
-        case EPI_RESID | EPI_NORM: launch_one<IO, EPI_RESID | EPI_NORM>(ctx, a); break;
-        case EPI_RESID: launch_one<IO, EPI_RESID>(ctx, a); break;
+        case EPI_NONE: launch_one<IO, EPI_NONE, false>(ctx, a); break;
+        case EPI_DOTAUX: launch_one<IO, EPI_DOTAUX, false>(ctx, a); break;
+        case EPI_NORM: launch_one<IO, EPI_NORM, false>(ctx, a); break;
+        case EPI_NORM | EPI_DOTIN: launch_one<IO, EPI_NORM | EPI_DOTIN, false>(ctx, a); break;
+        case EPI_RESID | EPI_NORM: launch_one<IO, EPI_RESID | EPI_NORM, false>(ctx, a); break;
+        case EPI_RESID: launch_one<IO, EPI_RESID, false>(ctx, a); break;
         default: disco_throw(DISCO_EINVAL, "stencil epilogue %d not built", epi);
     }
 }
@@ -486,28 +530,54 @@ void build_traversal(disco_ctx* ctx) {
     ctx->trav_kind = natural ? 0 : 1;
     HIPCHK(hipMalloc(&ctx->d_trav, sizeof(int2) * V));
     HIPCHK(hipMemcpy(ctx->d_trav, tr.data(), sizeof(int2) * V, hipMemcpyHostToDevice));
+    if (V % 2 == 0) {
+        std::vector<int2> par[2];
+        for (long k = 0; k < V; k++) {
+            const int c = tr[k].y;
+            par[((c & 0xff) + ((c >> 8) & 0xff) + ((c >> 16) & 0xff) + ((c >> 24) & 0xff)) & 1].push_back(tr[k]);
+        }
+        for (int p = 0; p < 2; p++) {
+            HIPCHK(hipMalloc(&ctx->d_trav_eo[p], sizeof(int2) * std::max<size_t>(1, par[p].size())));
+            HIPCHK(hipMemcpy(ctx->d_trav_eo[p], par[p].data(), sizeof(int2) * par[p].size(), hipMemcpyHostToDevice));
+        }
+    }
 }
 
-int stencil_nsb(disco_ctx* ctx, int n) {
+bool eo_supported(const disco_ctx* ctx) {
+    return ctx->dims[0] % 2 == 0 && ctx->dims[1] % 2 == 0 && ctx->dims[2] % 2 == 0 && ctx->dims[3] % 2 == 0 &&
+           ctx->d_trav_eo[0] != nullptr;
+}
+
+int stencil_nsb(disco_ctx* ctx, int n, bool eo) {
     int spb = stencil_spb(n);
-    return (int)((ctx->V + spb - 1) / spb);
+    const long sites = eo ? ctx->V / 2 : ctx->V;
+    return (int)((sites + spb - 1) / spb);
 }
 
 void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     REQUIRE(ctx->have_clover, DISCO_ESTATE, "operator applied before clover_setup");
     REQUIRE(c.nrhs >= 1 && c.nrhs <= kStencilBlock, DISCO_EINVAL, "nrhs per launch must be in 1..%d", kStencilBlock);
     REQUIRE(!(c.dagger && (c.epi & EPI_DOTIN)), DISCO_EINVAL, "DOTIN epilogue with dagger");
+    const bool eo = c.eo_target >= 0;
+    REQUIRE(!eo || (eo_supported(ctx) && c.eo_target <= 1 && !c.dagger && !(c.epi & EPI_RESID)), DISCO_EINVAL,
+            "even-odd stencil needs even extents, no dagger and no residual epilogue");
     StencilArgs a;
-    const size_t blk = native_bytes(ctx, c.prec, c.nrhs);
+    const size_t blk = native_bytes(ctx, c.prec, c.nrhs) / (eo ? 2 : 1);
     const int buf = blk < (1ULL << 32) ? 1 : 0;
     a.in = RoView{c.in, (unsigned)blk, buf};
     a.out = c.out;
     a.aux = RoView{c.aux, (unsigned)blk, buf};
     a.aux2 = RoView{c.aux2, (unsigned)blk, buf};
     a.mask = c.mask;
-    a.trav = ctx->d_trav;
+    a.trav = eo ? ctx->d_trav_eo[c.eo_target] : ctx->d_trav;
     a.part = c.part;
     a.V = ctx->V;
+    a.Vv = eo ? ctx->V / 2 : ctx->V;
+    a.nsites = (int)a.Vv;
+    a.eo_aux = eo && (c.ca != 0.0 || c.cg != 0.0 || (c.epi & EPI_DOTIN)) ? 1 : 0;
+    a.ca = c.ca;
+    a.cg = c.cg;
+    a.cb = c.cb;
     long st = 1;
     for (int m = 0; m < 4; m++) {
         a.L[m] = ctx->dims[m];
@@ -518,32 +588,32 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     a.kappa = ctx->kappa;
     a.n = c.nrhs;
     a.spb = stencil_spb(c.nrhs);
-    a.nsb = stencil_nsb(ctx, c.nrhs);
+    a.nsb = stencil_nsb(ctx, c.nrhs, eo);
     a.dagger = c.dagger;
     // staging pays once a site has 16 or more lanes sharing its links
     a.stage = ctx->opt_stage == 1 || (ctx->opt_stage == -1 && c.nrhs >= 16);
     double sp = c.prec == DISCO_F64 ? 8 : c.prec == DISCO_F32 ? 4 : 2;  // bytes per spinor real
     double sg = c.prec == DISCO_F64 ? 8 : 4;                             // bytes per link/clover real
-    int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & EPI_DOTAUX) ? 1 : 0);
-    double bytes = (double)ctx->V * (c.nrhs * nvec * 24 * sp + 72 * sg + 72 * sg + (c.mask ? 1 : 0));
-    int rec = prof_begin(ctx, 10 + c.prec);
-    if (c.prec == DISCO_F64) {
-        a.U = ctx->U64;
-        a.A = ctx->A64;
-        launch_epi<IO64>(ctx, a, c.epi);
-    } else if (c.prec == DISCO_F32) {
-        a.U = ctx->U32;
-        a.A = ctx->A32;
-        launch_epi<IO32>(ctx, a, c.epi);
-    } else if (c.prec == DISCO_BF16) {
-        a.U = ctx->U32;
-        a.A = ctx->A32;
-        launch_epi<IOBF>(ctx, a, c.epi);
-    } else {
+    int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & EPI_DOTAUX) ? 1 : 0) + (a.eo_aux ? 1 : 0);
+    // each spinor once, every link of the sites visited (all 4V links in even-odd
+    // mode, where the backward links belong to the other parity), clover once
+    double bytes = eo ? (double)a.Vv * (c.nrhs * nvec * 24 * sp + 144 * sg + 72 * sg + (c.mask ? 1 : 0))
+                      : (double)ctx->V * (c.nrhs * nvec * 24 * sp + 72 * sg + 72 * sg + (c.mask ? 1 : 0));
+    const int fam = (eo ? 13 : 10) + c.prec;
+    int rec = prof_begin(ctx, fam);
+    const bool f64 = c.prec == DISCO_F64;
+    a.U = f64 ? (const void*)ctx->U64 : (const void*)ctx->U32;
+    a.A = eo ? (f64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32) : (f64 ? (const void*)ctx->A64 : (const void*)ctx->A32);
+    if (c.prec == DISCO_F64)
+        launch_epi<IO64>(ctx, a, c.epi, eo);
+    else if (c.prec == DISCO_F32)
+        launch_epi<IO32>(ctx, a, c.epi, eo);
+    else if (c.prec == DISCO_BF16)
+        launch_epi<IOBF>(ctx, a, c.epi, eo);
+    else
         disco_throw(DISCO_EINVAL, "bad precision %d", c.prec);
-    }
     HIPCHK(hipGetLastError());
-    prof_end(ctx, rec, 10 + c.prec, bytes);
+    prof_end(ctx, rec, fam, bytes);
 }
 
 size_t native_bytes(const disco_ctx* ctx, int prec, int nrhs) {

@@ -1,0 +1,89 @@
+"""Parity at the larger workload shapes: 24^3x48 (the batching configuration,
+with regular and edge-remainder domains) and 32^3x64 (the production-sized
+lattice, with 8^3x16 and 16^3x32 domains).  The oracle cannot solve at these
+sizes in test time, so each solution is judged by the oracle's FP64 operator:
+the true relative residual of the full or domain-restricted system, computed
+on the host, must meet the tolerance, and must agree with the residual the
+library reports."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def disco():
+    import paper_2609_37049_amd as d
+    d.lib()
+    return d
+
+
+def _check(disco, ctx, U, A, pre, cut, inner, nrhs, seed, tol):
+    dom = ctx.domains(cut) if cut is not None else None
+    b = synth.random_spinor(ctx.V, nrhs, seed)
+    P = ctx.params(method=disco.BICGSTAB_DC, tol=tol, inner_prec=inner, rhs_block=nrhs)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, dom)
+    x = x.cpu().numpy()
+    for k in range(nrhs):
+        r = b[k] - oracle.dirac(U, A, pre.dims, BC, pre.kappa, x[k], cut=cut)
+        res = np.linalg.norm(r) / np.linalg.norm(b[k])
+        _say("  rhs %d: %d inner iterations, %d cycles, fallback %d, reported %.3e, oracle %.3e" %
+             (k, st[k].iters, st[k].outer_iters, st[k].fallback_used, st[k].true_rel_residual, res))
+        assert res <= tol * 1.05
+        assert abs(res - st[k].true_rel_residual) <= max(1e-2 * res, 2e-15)
+
+
+@pytest.fixture(scope="module")
+def batch_cfg(disco):
+    pre = synth.PRESETS["batch_24x24x24x48"]
+    _say("24^3x48: gauge field")
+    U = synth.gauge_field(pre.dims, pre.eps, pre.seed)
+    A = oracle.clover(U, pre.dims, pre.kappa, pre.csw)
+    ctx = disco.Context(pre.dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(pre.kappa, pre.csw)
+    return pre, ctx, U, A
+
+
+@pytest.mark.parametrize("domains", ["none", "regular", "remainder"])
+def test_batching_shape_24x24x24x48(disco, batch_cfg, domains):
+    pre, ctx, U, A = batch_cfg
+    if domains == "none":
+        cut = None
+    elif domains == "regular":
+        cut = synth.tiling_cuts(pre.dims, pre.block)
+    else:
+        cut = synth.offset_tiling_cuts(pre.dims, pre.block)
+    _say("24^3x48 FP32-inner solve, domains", domains)
+    _check(disco, ctx, U, A, pre, cut, disco.F32, 8, 61, 1e-10)
+
+
+@pytest.fixture(scope="module")
+def prod_cfg(disco):
+    pre = synth.PRESETS["prod_32x32x32x64"]
+    _say("32^3x64: gauge field")
+    U = synth.gauge_field(pre.dims, pre.eps, pre.seed)
+    A = oracle.clover(U, pre.dims, pre.kappa, pre.csw)
+    ctx = disco.Context(pre.dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(pre.kappa, pre.csw)
+    return pre, ctx, U, A
+
+
+@pytest.mark.parametrize("block", [None, (8, 8, 8, 16), (16, 16, 16, 32)])
+def test_production_shape_32x32x32x64(disco, prod_cfg, block):
+    pre, ctx, U, A = prod_cfg
+    cut = None if block is None else synth.tiling_cuts(pre.dims, block)
+    _say("32^3x64 BF16-storage solve, block", block)
+    _check(disco, ctx, U, A, pre, cut, disco.BF16, 4, 62, 1e-10)

@@ -226,3 +226,35 @@ def test_gain_of_trained_network(disco, medium, trained):
     _say("  Arnoldi steps to 1e-10: trained %d, untrained %d (gain %.2fx)" %
          (steps["trained"], steps["untrained"], steps["untrained"] / max(1, steps["trained"])))
     assert steps["trained"] < steps["untrained"]
+
+
+def test_training_over_ensembles_generalises(disco):
+    """Pairs from two seeded ensembles (training continues across gauge fields
+    with the transporters re-tabulated), evaluated on a held-out ensemble:
+    the trained network still beats the untrained one there."""
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.12, 1.0
+    ctx = disco.Context(dims, BC)
+    net = None
+    for seed in (71, 72):
+        ctx.gauge_set(synth.gauge_field(dims, 0.3, seed))
+        ctx.clover_setup(kappa, csw)
+        if net is None:
+            net = disco.Net(ctx, 16, 9)
+        else:
+            net.refresh()
+        st = net.train(32, snap_iters=(0, 8, 24, 64), batch=4, steps=60, lr=2e-3, seed=seed)
+        _say("  ensemble %d: loss %.4f -> %.4f" % (seed, st.first_loss, st.final_loss))
+    ctx.gauge_set(synth.gauge_field(dims, 0.3, 73))
+    ctx.clover_setup(kappa, csw)
+    net.refresh()
+    fresh = disco.Net(ctx, 16, 9)
+    b = ctx.dev(synth.random_spinor(ctx.V, 2, 74))
+    steps = {}
+    for name, m in (("trained", net), ("untrained", fresh)):
+        P = ctx.params(method=disco.FGMRES_NN, tol=1e-10, net=m, rhs_block=2)
+        _, st = ctx.solve_multi_rhs(b, P)
+        assert all(s.converged for s in st)
+        steps[name] = st[0].iters
+    _say("  held-out ensemble: trained %d, untrained %d Arnoldi steps" % (steps["trained"], steps["untrained"]))
+    assert steps["trained"] < steps["untrained"]
