@@ -272,6 +272,30 @@ int disco_correlator(disco_ctx* ctx, const void* L_full, const void* Lt_full, co
                      int ncfg, int T, const int* y0_set, int ny0, int vev_mode, void* C_full, void* C_fact, void* dC,
                      void* four_terms);
 
+/* The paper's region schedule (subsections "Domain decomposition of the
+ * propagator" and "Subtraction method"; multi-site sources of the Cost
+ * section).  For every operator time x0 the region is the temporal slab
+ * Lambda(x0) = {t : |t - x0| <= (delta-1)/2} (mod T) over all space, delta odd
+ * and below T.  disco_slab_sets groups the operator times 0..T-1 greedily (in
+ * increasing x0) into sets whose slabs are pairwise disjoint mod T (circular
+ * distance >= delta): masks[k] (host, room for T entries) gets the bits of
+ * set k, *nsets the number of sets.  Host only. */
+int disco_slab_sets(int T, int delta, int* nsets, unsigned long long* masks);
+/* L[g][x0] = the loop of D_{Lambda(x0)}^-1 at x0 (as disco_loops) for every
+ * x0, each set of disco_slab_sets solved as one multi-site source per (i,
+ * alpha) on the partition cut at the faces of its slabs (slabs of one set are
+ * disjoint; the rest of the time axis forms source-free domains).  Vev, w,
+ * gammas, L, tau_out, agg as in disco_loops_distill (tau_out receives
+ * tau_{Lambda(x0)}(x0, x0)).  These are the factorised loops of the
+ * subtracted correlator: pass them as L_blk / Lt_blk to disco_correlator. */
+int disco_loops_slab(disco_ctx* ctx, const void* Vev, int nv, const double* w, const int* gammas, int ngamma,
+                     int delta, const disco_solver_params* p, void* L, void* tau_out, disco_solver_stats* agg);
+/* Gaussian distillation profiles (the Gaussian-profiled subsection): the
+ * diagonal elemental weight |g_k(lambda)|^2 with g_k(lambda) =
+ * exp(-lambda^2 / (2 (0.8 omega_k)^2)), i.e. w = exp(-lambda^2 / (0.8 omega)^2),
+ * for n eigenvalues (host arrays; omega > 0).  Use as w of the loop calls. */
+int disco_profile_weights(const double* lambda, long n, double omega, double* w);
+
 /* Autotuner: time a fixed number of inner BiCGStab iterations (FP32 or BF16
  * storage, the full operator when dom is NULL) for right-hand-side blocks of
  * 4, 8, 16 and 32 on device-generated random sources, and keep the block with

@@ -425,3 +425,38 @@ def correlator(L_full, Lt_full, L_blk, Lt_blk, y0s=None, vev_mode=1):
         _cov(dL, dLt, y0s, vev_mode),
     ])
     return C_full, C_fact, C_full - C_fact, four
+
+
+# --------------------------------------------------------------------------
+# the paper's region schedule and Gaussian profiles
+# --------------------------------------------------------------------------
+
+def slab_cut(dims, x0: int, delta: int) -> np.ndarray:
+    """Cut masks of the partition whose region around operator time x0 is the
+    temporal slab {t : |t - x0| <= h} (mod T), h = (delta-1)/2, over all space
+    (Domain decomposition subsection): faces after x0+h and after x0-h-1."""
+    T = dims[3]
+    h = (delta - 1) // 2
+    cut = np.zeros((4, max(dims)), dtype=np.uint8)
+    cut[3, (x0 + h) % T] = 1
+    cut[3, (x0 - h - 1) % T] = 1
+    return cut
+
+
+def slab_loops(U, A, dims, bc, kappa, Vt, delta: int, codes, w=None, tol=1e-13):
+    """L[g][x0]: the loop of D_Lambda(x0)^-1 at x0 for every operator time x0,
+    each solved on its own (no multi-site packing)."""
+    T = dims[3]
+    nv = Vt.shape[1]
+    tau = np.empty((T, nv, 4, nv, 4), dtype=np.complex128)
+    for x0 in range(T):
+        tau[x0] = perambulator_tt(U, A, dims, bc, kappa, Vt, x0, slab_cut(dims, x0, delta), tol)
+    return loops(tau, codes, w), tau
+
+
+def profile_weights(lam, omega: float) -> np.ndarray:
+    """|g_k(lambda)|^2 for the Gaussian profile g_k(lambda) =
+    exp(-lambda^2 / (2 (0.8 omega_k)^2)) (Gaussian-profiled subsection)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    g = np.exp(-lam ** 2 / (2.0 * (0.8 * omega) ** 2))
+    return np.abs(g) ** 2

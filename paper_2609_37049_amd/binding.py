@@ -96,6 +96,9 @@ _SIGS.update({
     "disco_set_option": ([P, I, I], I),
     "disco_autotune": ([P, P, I, ctypes.POINTER(I), P], I),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
+    "disco_slab_sets": ([I, I, ctypes.POINTER(I), P], I),
+    "disco_loops_slab": ([P, P, I, P, P, I, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
+    "disco_profile_weights": ([P, ctypes.c_long, D, P], I),
     "disco_net_create": ([P, I, ctypes.c_ulonglong, P], I),
     "disco_net_destroy": ([P], I),
     "disco_net_refresh": ([P], I),
@@ -410,6 +413,35 @@ class Context:
                                             g.ctypes.data_as(P), len(g), ctypes.byref(params), _dptr(L), _dptr(tau),
                                             ctypes.byref(agg)))
         return L, tau, agg
+
+    def slab_sets(self, delta):
+        T = self.dims[3]
+        n = I()
+        m = (ctypes.c_ulonglong * T)()
+        rc = lib().disco_slab_sets(T, int(delta), ctypes.byref(n), ctypes.cast(m, P))
+        if rc != OK:
+            raise DiscoError(rc, "bad slab width %r" % (delta,))
+        return [int(m[k]) for k in range(n.value)]
+
+    def loops_slab(self, Vev, gammas, delta, params: SolverParams, w=None, want_tau=False):
+        torch = _torch()
+        T, nv = Vev.shape[0], Vev.shape[1]
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+        L = torch.empty((len(g), T), dtype=torch.complex128, device=Vev.device)
+        tau = torch.empty((T, nv, 4, nv, 4), dtype=torch.complex128, device=Vev.device) if want_tau else None
+        agg = SolverStats()
+        self._chk(lib().disco_loops_slab(self.h, _dptr(Vev), nv, _dptr(w), g.ctypes.data_as(P), len(g), int(delta),
+                                         ctypes.byref(params), _dptr(L), _dptr(tau), ctypes.byref(agg)))
+        return L, tau, agg
+
+    @staticmethod
+    def profile_weights(lam, omega):
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+        w = np.empty_like(lam)
+        rc = lib().disco_profile_weights(lam.ctypes.data_as(P), lam.size, float(omega), w.ctypes.data_as(P))
+        if rc != OK:
+            raise DiscoError(rc, "bad profile width %r" % (omega,))
+        return w
 
     def perambulators_tt(self, Vev, tmask, params: SolverParams, tau, dom: Domains | None = None):
         agg = SolverStats()

@@ -967,4 +967,109 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
     return rs;
 }
 
+// ---------------------------------------------------------------- region schedule
+// The paper's own regions: for every operator time x0 a temporal slab
+// Lambda(x0) = {t : |t - x0| <= h} (mod T), h = (delta - 1)/2, over the whole
+// spatial volume (subsections "Domain decomposition of the propagator" and
+// "Subtraction method"; the width delta is odd).  Operator times whose slabs
+// are disjoint mod T (circular distance >= delta) share one multi-site solve
+// (the Cost section): they are grouped greedily in increasing x0.
+static std::vector<unsigned long long> slab_sets(int T, int delta) {
+    std::vector<std::vector<int>> sets;
+    for (int x0 = 0; x0 < T; x0++) {
+        bool placed = false;
+        for (auto& set : sets) {
+            bool ok = true;
+            for (int y : set) {
+                const int d = std::abs(x0 - y);
+                if (std::min(d, T - d) < delta) ok = false;
+            }
+            if (ok) {
+                set.push_back(x0);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) sets.push_back({x0});
+    }
+    std::vector<unsigned long long> masks;
+    for (auto& set : sets) {
+        unsigned long long m = 0;
+        for (int y : set) m |= 1ULL << y;
+        masks.push_back(m);
+    }
+    return masks;
+}
+
+int disco_slab_sets(int T, int delta, int* nsets, unsigned long long* masks) {
+    if (T < 1 || T > 64 || delta < 1 || delta % 2 == 0 || delta >= T || !nsets) return DISCO_EINVAL;
+    const auto m = slab_sets(T, delta);
+    *nsets = (int)m.size();
+    if (masks)
+        for (size_t k = 0; k < m.size(); k++) masks[k] = m[k];
+    return DISCO_OK;
+}
+
+int disco_profile_weights(const double* lambda, long n, double omega, double* w) {
+    if (!lambda || !w || n < 0 || !(omega > 0)) return DISCO_EINVAL;
+    const double s = 0.8 * omega;
+    for (long k = 0; k < n; k++) w[k] = std::exp(-(lambda[k] * lambda[k]) / (s * s));
+    return DISCO_OK;
+}
+
+int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, const int* gammas, int ngamma, int delta,
+                     const disco_solver_params* P, void* L, void* tau_out, disco_solver_stats* agg) {
+    if (!ctx) return DISCO_EINVAL;
+    void* tau = tau_out;
+    std::vector<unsigned long long> sets;
+    int rc = guarded(ctx, [&] {
+        const int T = ctx->dims[3];
+        REQUIRE(Vin && gammas && P && L && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
+        REQUIRE(delta >= 1 && delta % 2 == 1 && delta < T, DISCO_EINVAL, "slab width must be odd and below T");
+        REQUIRE(T <= 64, DISCO_EINVAL, "at most 64 timeslices");
+        if (!tau) tau = ws_get(ctx, "ls_tau", sizeof(double2) * (size_t)T * nv * 4 * nv * 4);
+        sets = slab_sets(T, delta);
+    });
+    if (rc != DISCO_OK) return rc;
+    const int T = ctx->dims[3];
+    const int h = (delta - 1) / 2;
+    int lmax = 0;
+    for (int m = 0; m < 4; m++) lmax = std::max(lmax, ctx->dims[m]);
+    long long solves = 0;
+    disco_solver_stats tot{};
+    tot.converged = 1;
+    int status = DISCO_OK;
+    std::string err;
+    for (unsigned long long msk : sets) {
+        std::vector<uint8_t> cut(4 * (size_t)lmax, 0);
+        for (int x0 = 0; x0 < T; x0++)
+            if ((msk >> x0) & 1ULL) {
+                cut[3 * lmax + (x0 + h) % T] = 1;
+                cut[3 * lmax + ((x0 - h - 1) % T + T) % T] = 1;
+            }
+        disco_domains* dom = nullptr;
+        int rd = disco_domains_create(ctx, cut.data(), lmax, &dom);
+        if (rd != DISCO_OK) return rd;
+        disco_solver_stats a{};
+        int rs = disco_perambulators_tt(ctx, dom, Vin, nv, msk, P, tau, &a);
+        const long long ns = ctx->last_solves;
+        if (rs == DISCO_ENOCONV) err = ctx->err;
+        disco_domains_destroy(dom);
+        if (rs != DISCO_OK && rs != DISCO_ENOCONV) return rs;
+        if (rs == DISCO_ENOCONV) status = DISCO_ENOCONV;
+        solves += ns;
+        tot.iters = (int)std::min<long long>((long long)tot.iters + a.iters, 2147483647LL);
+        tot.outer_iters += a.outer_iters;
+        tot.fallback_used |= a.fallback_used;
+        tot.converged &= a.converged;
+        tot.true_rel_residual = std::max(tot.true_rel_residual, a.true_rel_residual);
+    }
+    if (agg) *agg = tot;
+    int rl = disco_loops(ctx, tau, T, nv, w, gammas, ngamma, L);
+    ctx->last_solves = solves;
+    if (rl != DISCO_OK) return rl;
+    if (status == DISCO_ENOCONV) ctx->err = err;
+    return status;
+}
+
 }  // extern "C"

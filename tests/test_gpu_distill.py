@@ -285,3 +285,43 @@ def test_full_size_eigvecs(disco):
         assert np.abs(w - lam[t]).max() < 1e-8
         A = Vn[t].reshape(pre.nv, -1)
         assert np.abs(np.conj(A) @ A.T - np.eye(pre.nv)).max() < 1e-11
+
+
+@pytest.mark.parametrize("delta", [1, 3, 5])
+def test_slab_schedule_loops(disco, delta):
+    """The paper's regions: a temporal slab of width delta centred on every
+    operator time x0, solved set by set with multi-site sources on the GPU,
+    against the oracle solving every x0 on its own; plus the Gaussian-profiled
+    loops from the same perambulators (weights from each side's own
+    eigenvalues)."""
+    dims = (4, 4, 4, 8)
+    kappa, csw = 0.12, 1.0
+    codes = [disco.G_1, disco.G_5, disco.G_X, disco.G_Y, disco.G_Z]
+    U = synth.gauge_field(dims, 0.3, 91)
+    A = oracle.clover(U, dims, kappa, csw)
+    Us = oracle.ape_smear(U, dims, 0.5, 2)
+    Vo, lam_o = oracle.laplace_eigvecs(Us, dims, 4)
+    Lo, tau_o = oracle.slab_loops(U, A, dims, BC, kappa, Vo, delta, codes)
+    ctx = _ctx(disco, dims, U, kappa, csw)
+    ctx.ape_smear(2, 0.5)
+    Vg, lam_g = ctx.laplace_eigvecs(4, 1e-13)
+    sets = ctx.slab_sets(delta)
+    T = dims[3]
+    assert sorted(sum(([t for t in range(T) if (m >> t) & 1] for m in sets), [])) == list(range(T))
+    P = ctx.params(method=disco.BICGSTAB_DC, tol=1e-12, inner_prec=disco.F32, rhs_block=8)
+    L, tau_g, st = ctx.loops_slab(Vg, codes, delta, P, want_tau=True)
+    _say("  slab delta %d: %d sets, %d solves, worst residual %.2e" % (delta, len(sets), ctx.last_solves(),
+                                                                       st.true_rel_residual))
+    assert ctx.last_solves() == len(sets) * 16
+    L = L.cpu().numpy()
+    for g in range(len(codes)):
+        err = np.abs(L[g] - Lo[g]).max() / np.abs(Lo[g]).max()
+        assert err < 1e-10, (g, err)
+    for omega in (0.05, 0.287):
+        wg = ctx.profile_weights(lam_g, omega)
+        wo = oracle.profile_weights(lam_o, omega)
+        Lw = ctx.loops(tau_g, codes, ctx.dev(wg)).cpu().numpy()
+        Lwo = oracle.loops(tau_o, codes, wo)
+        for g in range(len(codes)):
+            err = np.abs(Lw[g] - Lwo[g]).max() / max(np.abs(Lwo[g]).max(), 1e-300)
+            assert err < 1e-9, (omega, g, err)
