@@ -120,6 +120,52 @@ def solver_comparison(ctx, d, Vev, inner, tuned, T):
     return out, nn_roof
 
 
+def slab_schedule_cost(ctx, d, Vev, inner, tuned, nv_sub=4, delta=7):
+    """The paper's region schedule on the first nv_sub eigenvectors: loops of
+    the full operator for every timeslice, and loops of the slab-restricted
+    operator (slab of width delta centred on every operator time) solved with
+    multi-site sources and, for comparison, one operator time at a time.
+    Context for the paper's cost statements (packing gain, total cost ratio);
+    not part of the timed steps."""
+    import torch
+    T = ctx.dims[3]
+    h = (delta - 1) // 2
+    V4 = Vev[:, :nv_sub].contiguous()
+    codes = [d.G_5]
+    P = ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=inner, rhs_block=tuned)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    (_, _, _), t_full = timed(lambda: ctx.loops_distill(V4, codes, P))
+    n_full = ctx.last_solves()
+    (_, _, _), t_packed = timed(lambda: ctx.loops_slab(V4, codes, delta, P))
+    n_packed = ctx.last_solves()
+    tau = torch.zeros((T, nv_sub, 4, nv_sub, 4), dtype=torch.complex128, device="cuda:0")
+
+    def unpacked():
+        n = 0
+        for x0 in range(T):
+            cut = np.zeros((4, max(ctx.dims)), dtype=np.uint8)
+            cut[3, (x0 + h) % T] = 1
+            cut[3, (x0 - h - 1) % T] = 1
+            ctx.perambulators_tt(V4, 1 << x0, P, tau, ctx.domains(cut))
+            n += ctx.last_solves()
+        return n
+    n_unpacked, t_unpacked = timed(unpacked)
+    print("slab schedule: full %.2f s, packed %.2f s, unpacked %.2f s" % (t_full, t_packed, t_unpacked),
+          file=sys.stderr, flush=True)
+    return {"delta": delta, "nv": nv_sub, "full_solves": n_full, "full_s": round(t_full, 3),
+            "slab_solves_packed": n_packed, "slab_packed_s": round(t_packed, 3),
+            "slab_solves_unpacked": n_unpacked, "slab_unpacked_s": round(t_unpacked, 3),
+            "packing_speedup": round(t_unpacked / t_packed, 2),
+            "cost_ratio_full_plus_slab_over_full": round((t_full + t_packed) / t_full, 3)}
+
+
 def cpu_baseline(pre, seconds_budget=30.0):
     """The oracle on the host cores: one full-operator CGNR solve of the same
     workload to 1e-10 plus its projection at the source timeslice."""
@@ -263,6 +309,7 @@ def main():
             "alg_bytes_per_launch": round(by / max(nl, 1)),
             "flop_per_launch": FLOP_PER_SITE_RHS * sites * blk}
     comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
+    slab = slab_schedule_cost(ctx, d, Vev, inner, args.rhs_block or tuned)
     out = {
         "metric": METRIC, "value": round(rhs / dt, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
@@ -278,6 +325,7 @@ def main():
         "roofline": roof,
         "solver_comparison": comparison,
         "nn_roofline": nn_roof,
+        "slab_schedule": slab,
         "worst_true_rel_residual": worst,
         "inner_iterations": iters,
         "setup_s": round(setup_s, 3),

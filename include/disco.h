@@ -172,7 +172,10 @@ typedef struct {
     int rhs_block;     /* right-hand sides per batched launch; 0 = the autotuned block for
                         * inner_prec if disco_autotune ran, else 16 */
     int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
-    int check_every;   /* iterations between host convergence checks (0 = default) */
+    int check_every;   /* iterations between host convergence checks (0 = default: 2 for
+                        * BICGSTAB_DC, whose inner solves first run, without checks, as many
+                        * iterations as the previous inner solve of the same system took; 10
+                        * for CGNR_F64) */
     int restart;       /* FGMRES_NN: Krylov vectors per cycle (1..32, 0 = 16) */
     const disco_net* net; /* FGMRES_NN: the preconditioner (required) */
 } disco_solver_params;

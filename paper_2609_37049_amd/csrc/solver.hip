@@ -524,9 +524,11 @@ static void op_apply(Work& w, const InnerOp& op, int prec, const void* in, void*
 }
 
 // inner BiCGStab on op e = rin (normalised defect) in storage IO
+// hint: iterations the previous inner solve of this system took; that many
+// chunks (less one) run back to back before the host first reads the state.
 template <class IO>
 static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void* e, const uint8_t* mask,
-                    double inner_tol, int max_iter, int check_every) {
+                    double inner_tol, int max_iter, int check_every, int hint = 0) {
     disco_ctx* ctx = w.ctx;
     const long Vfull = w.V;
     w.V = op.Vv;  // vector helpers below work on the operator's vectors
@@ -595,6 +597,7 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
         }
     }
     int it = 0;
+    int blind = std::max(0, hint - check_every) / check_every;
     while (it < max_iter) {
         if (exec && max_iter - it >= check_every) {
             HIPCHK(hipGraphLaunch(exec, ctx->stream));
@@ -603,6 +606,10 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
             for (int k = 0; k < check_every && it < max_iter; k++, it++) iteration();
         }
         HIPCHK(hipGetLastError());
+        if (blind > 0) {
+            blind--;
+            continue;
+        }
         pull(w);
         bool any = false;
         for (auto& sc : w.h) any |= sc.active != 0;
@@ -681,7 +688,7 @@ __global__ void k_eo_clover_inv(const void* __restrict__ in, void* __restrict__ 
 //   e_o = A_oo^-1 (r_o + kappa H_oe e_e).
 template <class IO>
 static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol,
-                       int max_iter, int check_every) {
+                       int max_iter, int check_every, int hint = 0) {
     disco_ctx* ctx = w.ctx;
     const long V = w.V;
     const int n = w.n;
@@ -705,7 +712,7 @@ static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_
     op.eo = true;
     op.Vv = V / 2;
     op.nsb = disco::stencil_nsb(ctx, n, true);
-    const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every);
+    const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every, hint);
     disco::StencilCall cr{prec, 0, n, ee, eo, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
     disco::stencil_launch(ctx, cr);
     hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, ee, eo, e, V, n, Lx, Ly, Lz);
@@ -764,13 +771,14 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
     copy_scale<IO64, IO64>(w, b64, r64, 0);
     int iters = 0, outer = 0;
     const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
-    const int check = P.check_every > 0 ? P.check_every : 10;
+    const int check = P.check_every > 0 ? P.check_every : 2;
     const double itol = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-5);
     const int inner_cap = 2000;
     const bool trace = getenv("DISCO_TRACE") != nullptr;
     const bool use_eo = ctx->opt_eo && disco::eo_supported(ctx);
     double last_worst = 1e300;
     int stall = 0;
+    int hint = 0;
     while (true) {
         pull(w);
         bool done = true;
@@ -790,14 +798,17 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
         if (stall >= 3) break;  // no progress: leave it to the fallback
         outer++;
         copy_scale<IO64, IO>(w, r64, rin, 1);
+        int ran;
         if (use_eo) {
-            iters += bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+            ran = bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint);
         } else {
             InnerOp op;
             op.Vv = w.V;
             op.nsb = w.nsb;
-            iters += bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check);
+            ran = bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint);
         }
+        iters += ran;
+        hint = ran;
         dc_update<IO>(w, x64, e);
         outer_residual(w, b64, x64, r64, mask, tol2);
     }
