@@ -299,6 +299,29 @@ int disco_loops_slab(disco_ctx* ctx, const void* Vev, int nv, const double* w, c
  * for n eigenvalues (host arrays; omega > 0).  Use as w of the loop calls. */
 int disco_profile_weights(const double* lambda, long n, double omega, double* w);
 
+/* Connected contraction (equation Cfull: C = C^(c) + C^(d)) in distillation.
+ * disco_perambulators_all: for every source timeslice ts in tmask (0 = all) and
+ * every (i, alpha), solve D x = v_i(ts) (x) e_alpha and project the solution at
+ * every sink timeslice: tau_all (device, [T][T][nv][4][nv][4] complex128) =
+ * tau_all[ts][tk][j][beta][i][alpha] = (V(tk)^+ D^-1 V(ts)).  agg as in
+ * disco_loops_distill.  T <= 64. */
+int disco_perambulators_all(disco_ctx* ctx, const void* Vev, int nv, unsigned long long tmask,
+                            const disco_solver_params* p, void* tau_all, disco_solver_stats* agg);
+/* C[g][dt] (device, [ngamma][T] complex128), averaged over the source times
+ * y0 (host list; NULL = all T), x0 = y0 + dt mod T:
+ *   C = -Tr[Phi_Gamma(x0) tau(x0,y0) Phi_Gammatilde(y0) tau(y0,x0)]
+ * with Phi_Gamma(t) = Gamma (x) diag(w(t)) (w device [T][nv] or NULL = 1),
+ * Gamma~ = gamma_4 Gamma^+ gamma_4, and tau(y0,x0) = g5 tau(x0,y0)^+ g5
+ * (gamma_5-hermiticity), so only the sources at y0 are needed.  The minus
+ * sign is the fermion loop of the connected Wick contraction; the loops
+ * carry no sign, so C_full = C + C^(d) and the paper's noise-reduced
+ * estimator is C^NR = C + dC (dC from disco_correlator). */
+int disco_connected(disco_ctx* ctx, const void* tau_all, int T, int nv, const double* w, const int* gammas,
+                    int ngamma, const int* y0_set, int ny0, void* C);
+/* a m_eff(t) = ln(C(t) / C(t+1)) for t = 0 .. n-2 (host; NaN where the ratio is
+ * not positive), the effective mass of the Gaussian-profiled subsection. */
+int disco_effective_mass(const double* C, int n, double* meff);
+
 /* Autotuner: time a fixed number of inner BiCGStab iterations (FP32 or BF16
  * storage, the full operator when dom is NULL) for right-hand-side blocks of
  * 4, 8, 16 and 32 on device-generated random sources, and keep the block with

@@ -460,3 +460,52 @@ def profile_weights(lam, omega: float) -> np.ndarray:
     lam = np.asarray(lam, dtype=np.float64)
     g = np.exp(-lam ** 2 / (2.0 * (0.8 * omega) ** 2))
     return np.abs(g) ** 2
+
+
+# --------------------------------------------------------------------------
+# connected contraction (equation Cfull)
+# --------------------------------------------------------------------------
+
+def perambulator_all(U, A, dims, bc, kappa, Vt, ts: int, tol=1e-13) -> np.ndarray:
+    """tau[tk][j][beta][i][alpha] = V(tk)^+ D^-1 V(ts) for every sink tk."""
+    T = dims[3]
+    nv = Vt.shape[1]
+    tau = np.empty((T, nv, 4, nv, 4), dtype=np.complex128)
+    for i in range(nv):
+        X = []
+        for a in range(4):
+            x, _, _ = cgnr(U, A, dims, bc, kappa, source(Vt, dims, ts, i, a), None, tol)
+            X.append(x)
+        X = np.stack(X)
+        for tk in range(T):
+            tau[tk, :, :, i, :] = project(Vt, dims, X, tk)
+    return tau
+
+
+def connected(tau_all, codes, w=None, y0s=None) -> np.ndarray:
+    """C[g][dt] = -(1/|Y|) sum_{y0} Tr[Phi_G(x0) tau(x0,y0) Phi_Gt(y0) tau(y0,x0)],
+    x0 = y0+dt mod T, Phi_G(t) = Gamma (x) diag(w(t)), Gamma~ = g4 Gamma^+ g4,
+    with both directions taken from direct solves (tau_all[ts][tk] =
+    V(tk)^+ D^-1 V(ts)): the sink-to-source perambulator tau(y0,x0) comes from
+    the sources at x0, not from gamma_5-hermiticity."""
+    T = tau_all.shape[0]
+    nv = tau_all.shape[2]
+    y0s = list(range(T)) if y0s is None else list(y0s)
+    g4 = gamma(3)
+    out = np.zeros((len(codes), T), dtype=np.complex128)
+    for gi, c in enumerate(codes):
+        G = channel_matrix(c)
+        Gt = g4 @ np.conj(G.T) @ g4
+        for dt in range(T):
+            acc = 0j
+            for y0 in y0s:
+                x0 = (y0 + dt) % T
+                wx = np.ones(nv) if w is None else w[x0]
+                wy = np.ones(nv) if w is None else w[y0]
+                Phi_x = np.kron(np.diag(wx), G)      # index j*4 + beta
+                Phi_y = np.kron(np.diag(wy), Gt)
+                fwd = tau_all[y0, x0].reshape(4 * nv, 4 * nv)   # tau(x0, y0)
+                bwd = tau_all[x0, y0].reshape(4 * nv, 4 * nv)   # tau(y0, x0)
+                acc += np.trace(Phi_x @ fwd @ Phi_y @ bwd)
+            out[gi, dt] = -acc / len(y0s)
+    return out

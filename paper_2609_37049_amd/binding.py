@@ -99,6 +99,10 @@ _SIGS.update({
     "disco_slab_sets": ([I, I, ctypes.POINTER(I), P], I),
     "disco_loops_slab": ([P, P, I, P, P, I, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
     "disco_profile_weights": ([P, ctypes.c_long, D, P], I),
+    "disco_perambulators_all": ([P, P, I, ctypes.c_ulonglong, ctypes.POINTER(SolverParams), P,
+                                 ctypes.POINTER(SolverStats)], I),
+    "disco_connected": ([P, P, I, I, P, P, I, P, I, P], I),
+    "disco_effective_mass": ([P, I, P], I),
     "disco_net_create": ([P, I, ctypes.c_ulonglong, P], I),
     "disco_net_destroy": ([P], I),
     "disco_net_refresh": ([P], I),
@@ -433,6 +437,35 @@ class Context:
         self._chk(lib().disco_loops_slab(self.h, _dptr(Vev), nv, _dptr(w), g.ctypes.data_as(P), len(g), int(delta),
                                          ctypes.byref(params), _dptr(L), _dptr(tau), ctypes.byref(agg)))
         return L, tau, agg
+
+    def perambulators_all(self, Vev, params: SolverParams, tmask=0):
+        torch = _torch()
+        T, nv = Vev.shape[0], Vev.shape[1]
+        tau = torch.zeros((T, T, nv, 4, nv, 4), dtype=torch.complex128, device=Vev.device)
+        agg = SolverStats()
+        self._chk(lib().disco_perambulators_all(self.h, _dptr(Vev), nv, int(tmask), ctypes.byref(params), _dptr(tau),
+                                                ctypes.byref(agg)))
+        return tau, agg
+
+    def connected(self, tau_all, gammas, w=None, y0s=None):
+        torch = _torch()
+        T, nv = tau_all.shape[0], tau_all.shape[2]
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+        y = None if y0s is None else np.ascontiguousarray(np.asarray(y0s, dtype=np.int32))
+        C = torch.empty((len(g), T), dtype=torch.complex128, device=tau_all.device)
+        self._chk(lib().disco_connected(self.h, _dptr(tau_all), T, nv, _dptr(w), g.ctypes.data_as(P), len(g),
+                                        None if y is None else y.ctypes.data_as(P), 0 if y is None else len(y),
+                                        _dptr(C)))
+        return C
+
+    @staticmethod
+    def effective_mass(C):
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        m = np.empty(len(C) - 1, dtype=np.float64)
+        rc = lib().disco_effective_mass(C.ctypes.data_as(P), len(C), m.ctypes.data_as(P))
+        if rc != OK:
+            raise DiscoError(rc, "effective mass needs at least two values")
+        return m
 
     @staticmethod
     def profile_weights(lam, omega):

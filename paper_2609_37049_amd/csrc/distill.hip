@@ -445,6 +445,70 @@ __global__ void k_loops(const double2* __restrict__ tau, int T, int nv, const do
     if (threadIdx.x == 0) L[(long)g * T + t] = make_double2(acc[0], acc[1]);
 }
 
+// tau_all[ts][tk][j][beta][i][alpha] <- C[tk][j][beta*n + r] (sinks tk0 .. tk0+nk-1)
+__global__ void k_tau_scatter_all(const double2* __restrict__ C, const SrcSpec* __restrict__ spec,
+                                  double2* __restrict__ tau, int nv, int n, int ts, int T, int tk0, int nk) {
+    const long per = (long)nv * 4 * n;
+    const long tot = per * nk;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        const int kk = (int)(q / per);
+        const int rem0 = (int)(q - kk * per);
+        const int j = rem0 / (4 * n), rem = rem0 - j * 4 * n;
+        const int beta = rem / n, r = rem - beta * n;
+        const int i = spec[r].i, a = spec[r].alpha;
+        const long tk = tk0 + kk;
+        tau[(((((long)ts * T + tk) * nv + j) * 4 + beta) * nv + i) * 4 + a] = C[q];
+    }
+}
+
+// Connected correlator from all-to-all perambulators, with the source-to-sink
+// direction from gamma_5-hermiticity, tau(y0,x0) = g5 tau(x0,y0)^+ g5:
+//   C[g][dt] = -(1/|Y|) sum_{y0} sum_{j,i} w_j(x0) w_i(y0)
+//              sum_{b,a} (Gamma tau_ji Gamma~)[b][a] g5_b g5_a conj(tau_ji[b][a]),
+// x0 = y0 + dt (mod T), tau_ji[b][a] = tau(x0,y0)[j][b][i][a], Gamma~ = g4 Gamma^+ g4.
+// One block per (g, dt); fixed summation order.
+__global__ void k_connected(const double2* __restrict__ tau, int T, int nv, const double* __restrict__ w,
+                            const int* __restrict__ gam, const int* __restrict__ y0s, int ny0, double2* __restrict__ Cout) {
+    const int g = blockIdx.x / T, dt = blockIdx.x % T;
+    const int ch = gam[g];
+    const double sg = ch == DISCO_G_1 ? 1.0 : -1.0;  // Gamma~ = sg * Gamma for 1, g5, g_k
+    double acc[2] = {0, 0};
+    for (int k = 0; k < ny0; k++) {
+        const int y0 = y0s[k], x0 = (y0 + dt) % T;
+        const double2* tp = tau + ((long)y0 * T + x0) * (long)(nv * 4) * (nv * 4);
+        for (int p = threadIdx.x; p < nv * nv; p += blockDim.x) {
+            const int j = p / nv, i = p % nv;
+            cd t[4][4];
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const double2 v = tp[(((long)j * 4 + b) * nv + i) * 4 + a];
+                    t[b][a] = mk(v.x, v.y);
+                }
+            cd sum = mk(0.0, 0.0);
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    cd m = mk(0.0, 0.0);  // (Gamma t Gamma)[b][a]
+                    for (int b2 = 0; b2 < 4; b2++) {
+                        const cd G1 = channel_entry(ch, b, b2);
+                        if (G1.re == 0 && G1.im == 0) continue;
+                        for (int a2 = 0; a2 < 4; a2++) {
+                            const cd G2 = channel_entry(ch, a2, a);
+                            if (G2.re == 0 && G2.im == 0) continue;
+                            m = m + G1 * t[b2][a2] * G2;
+                        }
+                    }
+                    const double s5 = ((b < 2) == (a < 2)) ? 1.0 : -1.0;
+                    sum = sum + s5 * (m * cj(t[b][a]));
+                }
+            const double wj = w ? w[(long)x0 * nv + j] : 1.0, wi = w ? w[(long)y0 * nv + i] : 1.0;
+            acc[0] += wj * wi * sg * sum.re;
+            acc[1] += wj * wi * sg * sum.im;
+        }
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0) Cout[(long)g * T + dt] = make_double2(-acc[0] / ny0, -acc[1] / ny0);
+}
+
 // Correlator of loops La, Lb [ncfg][T]: C(dt) = mean_{y0} [mean_c La(y0+dt) Lb(y0) - VEV]
 __device__ cd corr_one(const double2* La, const double2* Lb, int ncfg, int T, const int* y0s, int ny0, int vev_mode,
                        int dt) {
@@ -1070,6 +1134,118 @@ int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, c
     if (rl != DISCO_OK) return rl;
     if (status == DISCO_ENOCONV) ctx->err = err;
     return status;
+}
+
+// All-to-all perambulators for the connected correlator: sources on every
+// timeslice ts in tmask, each solution projected at every sink timeslice tk
+// (batched FP64 matrix-core contraction over the sinks):
+//   tau_all[ts][tk][j][beta][i][alpha] = V(tk)^+ D^-1 V(ts).
+int disco_perambulators_all(disco_ctx* ctx, const void* Vin, int nv, unsigned long long tmask,
+                            const disco_solver_params* P, void* tau_out, disco_solver_stats* agg) {
+    if (!ctx) return DISCO_EINVAL;
+    bool all_ok = true;
+    int rc = guarded(ctx, [&] {
+        REQUIRE(Vin && P && tau_out && nv > 0, DISCO_EINVAL, "bad argument");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "perambulators before clover_setup");
+        const int T = ctx->dims[3];
+        REQUIRE(T <= 64, DISCO_EINVAL, "at most 64 timeslices");
+        const unsigned long long all = T == 64 ? ~0ULL : ((1ULL << T) - 1);
+        if (tmask == 0) tmask = all;
+        REQUIRE((tmask & ~all) == 0, DISCO_EINVAL, "tmask names timeslices beyond T");
+        activate(ctx);
+        const long V = ctx->V, Vs = ctx->Vs, K = 3 * Vs;
+        double2* Vi = (double2*)ws_get(ctx, "ld_V", sizeof(double2) * T * K * nv);
+        k_eig_import<<<grid_for((long)T * nv * K), 256, 0, ctx->stream>>>((const double2*)Vin, Vi, T, K, nv);
+        const int nrhs_set = 4 * nv;
+        const int blk = disco::default_rhs_block(*P, nrhs_set, ctx);
+        const int kchunk = std::min(T, 8);  // sinks per batched contraction
+        SrcSpec* specd = (SrcSpec*)ws_get(ctx, "ld_spec", sizeof(SrcSpec) * blk);
+        double2* b64 = (double2*)ws_get(ctx, "ld_b64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* x64 = (double2*)ws_get(ctx, "ld_x64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* G = (double2*)ws_get(ctx, "la_G", sizeof(double2) * K * 4 * blk * kchunk);
+        double2* C = (double2*)ws_get(ctx, "la_C", sizeof(double2) * nv * 4 * blk * kchunk);
+        std::vector<disco_solver_stats> st(blk);
+        long long solves = 0, iters = 0;
+        double worst = 0;
+        int fb = 0, outer = 0;
+        for (int ts = 0; ts < T; ts++) {
+            if (!((tmask >> ts) & 1ULL)) continue;
+            for (int r0 = 0; r0 < nrhs_set; r0 += blk) {
+                const int n = std::min(blk, nrhs_set - r0);
+                std::vector<SrcSpec> spec(n);
+                for (int r = 0; r < n; r++) spec[r] = SrcSpec{1ULL << ts, (r0 + r) / 4, (r0 + r) % 4};
+                HIPCHK(hipMemcpyAsync(specd, spec.data(), sizeof(SrcSpec) * n, hipMemcpyHostToDevice, ctx->stream));
+                k_sources<<<grid_for(V * n), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, n);
+                HIPCHK(hipGetLastError());
+                disco::solve_native(ctx, nullptr, *P, n, b64, x64, st.data());
+                for (int r = 0; r < n; r++) {
+                    all_ok &= st[r].converged != 0;
+                    worst = std::max(worst, st[r].true_rel_residual);
+                }
+                iters += st[0].iters;
+                outer += st[0].outer_iters;
+                fb |= st[0].fallback_used;
+                solves += n;
+                for (int tk0 = 0; tk0 < T; tk0 += kchunk) {
+                    const int nk = std::min(kchunk, T - tk0);
+                    for (int kk = 0; kk < nk; kk++)
+                        k_slab<<<grid_for(Vs * 12 * n), 256, 0, ctx->stream>>>(x64, G + (long)kk * K * 4 * n, V, Vs,
+                                                                                n, tk0 + kk);
+                    zgemm_hn(ctx, Vi + (long)tk0 * K * nv, nv, K * nv, G, 4L * n, K * 4L * n, C, nv, 4 * n, (int)K, nk);
+                    k_tau_scatter_all<<<grid_for((long)nv * 4 * n * nk), 256, 0, ctx->stream>>>(
+                        C, specd, (double2*)tau_out, nv, n, ts, T, tk0, nk);
+                }
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+            }
+        }
+        if (agg) {
+            agg->iters = (int)std::min<long long>(iters, 2147483647LL);
+            agg->outer_iters = outer;
+            agg->fallback_used = fb;
+            agg->converged = all_ok;
+            agg->true_rel_residual = worst;
+        }
+        ctx->last_solves = solves;
+    });
+    if (rc == DISCO_OK && !all_ok) {
+        ctx->err = "a distillation solve missed the tolerance";
+        return DISCO_ENOCONV;
+    }
+    return rc;
+}
+
+int disco_connected(disco_ctx* ctx, const void* tau_all, int T, int nv, const double* w, const int* gammas, int ngamma,
+                    const int* y0_set, int ny0, void* C) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        REQUIRE(tau_all && gammas && C && T > 0 && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
+        for (int g = 0; g < ngamma; g++) REQUIRE(gammas[g] >= 0 && gammas[g] <= 4, DISCO_EINVAL, "bad channel");
+        std::vector<int> y0;
+        if (y0_set && ny0 > 0) {
+            for (int k = 0; k < ny0; k++) {
+                REQUIRE(y0_set[k] >= 0 && y0_set[k] < T, DISCO_EINVAL, "y0 out of range");
+                y0.push_back(y0_set[k]);
+            }
+        } else {
+            for (int t = 0; t < T; t++) y0.push_back(t);
+        }
+        activate(ctx);
+        int* gd = (int*)ws_get(ctx, "cn_g", sizeof(int) * ngamma);
+        int* yd = (int*)ws_get(ctx, "cn_y", sizeof(int) * y0.size());
+        HIPCHK(hipMemcpyAsync(gd, gammas, sizeof(int) * ngamma, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(yd, y0.data(), sizeof(int) * y0.size(), hipMemcpyHostToDevice, ctx->stream));
+        k_connected<<<ngamma * T, 256, 0, ctx->stream>>>((const double2*)tau_all, T, nv, w, gd, yd, (int)y0.size(),
+                                                          (double2*)C);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int disco_effective_mass(const double* C, int n, double* meff) {
+    if (!C || !meff || n < 2) return DISCO_EINVAL;
+    for (int t = 0; t + 1 < n; t++) meff[t] = (C[t] > 0 && C[t + 1] > 0) ? std::log(C[t] / C[t + 1]) : std::nan("");
+    return DISCO_OK;
 }
 
 }  // extern "C"

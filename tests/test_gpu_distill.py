@@ -325,3 +325,48 @@ def test_slab_schedule_loops(disco, delta):
         for g in range(len(codes)):
             err = np.abs(Lw[g] - Lwo[g]).max() / max(np.abs(Lwo[g]).max(), 1e-300)
             assert err < 1e-9, (omega, g, err)
+
+
+def test_connected_correlator_and_noise_reduced_estimator(disco):
+    """All-to-all perambulators on the GPU and the connected contraction (the
+    sink-to-source direction from gamma_5-hermiticity) against the oracle,
+    which takes both directions from direct solves; C^NR = C^(c) + dC and the
+    effective mass from the library's helper."""
+    dims = (4, 4, 4, 8)
+    kappa, csw = 0.12, 1.0
+    codes = [disco.G_1, disco.G_5, disco.G_X]
+    U = synth.gauge_field(dims, 0.3, 111)
+    A = oracle.clover(U, dims, kappa, csw)
+    Us = oracle.ape_smear(U, dims, 0.5, 2)
+    Vo, lam_o = oracle.laplace_eigvecs(Us, dims, 3)
+    T = dims[3]
+    tau_o = np.stack([oracle.perambulator_all(U, A, dims, BC, kappa, Vo, ts) for ts in range(T)])
+    Co = oracle.connected(tau_o, codes)
+    wo = oracle.profile_weights(lam_o, 0.287)
+    Cow = oracle.connected(tau_o, codes, wo, y0s=[0, 3, 5])
+    ctx = _ctx(disco, dims, U, kappa, csw)
+    ctx.ape_smear(2, 0.5)
+    Vg, lam_g = ctx.laplace_eigvecs(3, 1e-13)
+    P = ctx.params(method=disco.BICGSTAB_DC, tol=1e-12, inner_prec=disco.F32, rhs_block=12)
+    tau_g, st = ctx.perambulators_all(Vg, P)
+    assert ctx.last_solves() == T * 12
+    C = ctx.connected(tau_g, codes).cpu().numpy()
+    Cw = ctx.connected(tau_g, codes, ctx.dev(ctx.profile_weights(lam_g, 0.287)), y0s=[0, 3, 5]).cpu().numpy()
+    for g in range(len(codes)):
+        for a, r in ((C[g], Co[g]), (Cw[g], Cow[g])):
+            err = np.abs(a - r).max() / np.abs(r).max()
+            _say("  connected channel %d: rel error %.2e" % (codes[g], err))
+            assert err < 1e-10
+    # the pseudoscalar connected correlator is real and positive
+    assert np.abs(C[1].imag).max() < 1e-10 * np.abs(C[1].real).max()
+    assert (C[1].real > 0).all()
+    # noise-reduced estimator: connected + subtracted disconnected
+    dom = ctx.domains(synth.tiling_cuts(dims, (4, 4, 4, 4)))
+    Lf, _, _ = ctx.loops_distill(Vg, [disco.G_5], P)
+    Lb, _, _ = ctx.loops_distill(Vg, [disco.G_5], P, dom)
+    _, _, dC, _ = ctx.correlator(Lf, -Lf, Lb, -Lb)
+    CNR = C[1] + dC.cpu().numpy()
+    assert np.isfinite(CNR).all()
+    m = ctx.effective_mass(C[1].real[: T // 2 + 1])
+    ref = np.log(C[1].real[: T // 2] / C[1].real[1: T // 2 + 1])
+    assert np.abs(m - ref).max() < 1e-14
