@@ -65,6 +65,7 @@ def load_traffic(kernel_tag):
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def solver_comparison(ctx, d, Vev, inner, tuned, T):
@@ -292,6 +293,13 @@ def main():
     stats = {t: ctx.profile_get(fams[t]) for t in cands}
     kernel_tag = max(stats, key=lambda t: stats[t][0])
     nl, ms, by = stats[kernel_tag]
+    ml, mms, mfl = ctx.profile_get(d.K_MFMA)
+    mtf = mfl / (mms / 1e3) / 1e12 if mms > 0 else 0.0
+    mfma_roof = {"bound": "mfma", "achieved": round(mtf, 2), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(mtf / FP64_MFMA_PEAK_TFLOPS, 4),
+                 "kernel": "k_zgemm_hn (perambulator projection V(t)^+ X(t), FP64 matrix cores)",
+                 "launches": ml, "avg_launch_ms": round(mms / max(ml, 1), 4),
+                 "flop_per_launch": round(mfl / max(ml, 1))}
     sites = ctx.V // 2 if "_eo" in kernel_tag else ctx.V
     print("profiled step done: %d launches of %s" % (nl, kernel_tag), file=sys.stderr, flush=True)
     avg_ms = ms / max(nl, 1)
@@ -325,6 +333,7 @@ def main():
         "roofline": roof,
         "solver_comparison": comparison,
         "nn_roofline": nn_roof,
+        "perambulator_roofline": mfma_roof,
         "slab_schedule": slab,
         "worst_true_rel_residual": worst,
         "inner_iterations": iters,

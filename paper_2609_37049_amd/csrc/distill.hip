@@ -241,24 +241,43 @@ __global__ __launch_bounds__(64) void k_zgemm_hn(const double2* __restrict__ A, 
     const int kq = lane >> 4;
     const double2* Ab = A + (long)b * sA;
     const double2* Bb = B + (long)b * sB;
-    d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-    const int k0 = ks * kchunk, k1 = min(K, k0 + kchunk);
-    for (int kb = k0; kb < k1; kb += 4) {
-        const int k = kb + kq;
-        double2 a = (k < k1 && i < M) ? Ab[(long)k * lda + i] : make_double2(0, 0);
-        double2 v = (k < k1 && j < N) ? Bb[(long)k * ldb + j] : make_double2(0, 0);
-        // conj(a) * v = (ar br + ai bi) + i (ar bi - ai br)
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.x, cr, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, v.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, v.y, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, v.x, ci, 0, 0, 0);
+    // four k-steps per trip with independent accumulators, so the matrix-core
+    // pipeline is not stalled by a single dependency chain; all loads first
+    d4v cr[4], ci[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        cr[u] = d4v{0, 0, 0, 0};
+        ci[u] = d4v{0, 0, 0, 0};
     }
+    const int k0 = ks * kchunk, k1 = min(K, k0 + kchunk);
+    for (int kb = k0; kb < k1; kb += 16) {
+        double2 a[4], v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int k = kb + 4 * u + kq;
+            a[u] = (k < k1 && i < M) ? Ab[(long)k * lda + i] : make_double2(0, 0);
+            v[u] = (k < k1 && j < N) ? Bb[(long)k * ldb + j] : make_double2(0, 0);
+        }
+        // conj(a) * v = (ar br + ai bi) + i (ar bi - ai br)
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, v[u].x, cr[u], 0, 0, 0);
+            ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, v[u].y, ci[u], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, v[u].y, cr[u], 0, 0, 0);
+            ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, v[u].x, ci[u], 0, 0, 0);
+        }
+    }
+    d4v crs = (cr[0] + cr[1]) + (cr[2] + cr[3]);
+    d4v cis = (ci[0] + ci[1]) + (ci[2] + ci[3]);
     // accumulator layout of v_mfma_f64_16x16x4f64: register e of a lane holds
     // row lane/16 + 4e, column lane%16
     for (int e = 0; e < 4; e++) {
         const int row = ti * 16 + (lane >> 4) + 4 * e;
         const int col = tj * 16 + (lane & 15);
-        if (row < M && col < N) P[(((long)b * nks + ks) * M + row) * N + col] = make_double2(cr[e], ci[e]);
+        if (row < M && col < N) P[(((long)b * nks + ks) * M + row) * N + col] = make_double2(crs[e], cis[e]);
     }
 }
 
@@ -588,7 +607,7 @@ void zgemm_hn(disco_ctx* ctx, const double2* A, long lda, long sA, const double2
     // split K so that the launch has a few thousand wavefronts
     long tiles = (long)tilesM * tilesN * batch;
     int nks = (int)std::max(1L, std::min<long>(4096 / std::max(1L, tiles), (K + 63) / 64));
-    int kchunk = ((K + nks - 1) / nks + 3) / 4 * 4;
+    int kchunk = ((K + nks - 1) / nks + 15) / 16 * 16;
     nks = (K + kchunk - 1) / kchunk;
     double2* P = (double2*)ws_get(ctx, "gemm_part", sizeof(double2) * (size_t)batch * nks * M * N);
     int rec = prof_begin(ctx, 1);
