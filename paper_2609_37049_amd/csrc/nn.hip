@@ -378,6 +378,189 @@ __global__ __launch_bounds__(256) void k_nn_layer(const LayerArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ weights-first form
+// For a layer with one output channel (the last layer), and for the adjoint of
+// a layer with one input channel (the first layer's input gradient), contract
+// first and transport afterwards, so that only one channel is transported per
+// offset:
+//   Y_d(z) = sum_i R_d[i] psi_i(z)             (matrix cores, all 81 offsets)
+//   out(x) = sum_d M_d(x) Y_d(x + sgn d)       (one-channel colour transport)
+// forward: R_d[i] = W[d][0][i], M_d(x) = T_d(x), sgn = +1;
+// adjoint: R_d[o] = W[d][o][0]^+, M_d(x) = T_d(x - d)^+, sgn = -1.
+constexpr int kWfRows = 81 * 8;                 // (d, s, re/im)
+constexpr int kWfRowTiles = (kWfRows + 15) / 16;  // 41
+
+// fragments [rowtile 41][kstep 4][lane 64][8] of the (81*8) x 128 real block matrix
+__global__ void k_nn_wf_frag(const float* __restrict__ w, int ci, int co, int adj, uint16_t* __restrict__ frag) {
+    const long total = (long)kWfRowTiles * 4 * 64 * 8;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+        const int ks = (int)((idx >> 9) & 3);
+        const int rt = (int)(idx >> 11);
+        const int row = rt * 16 + (lane & 15);
+        const int kk = ks * 32 + 8 * (lane >> 4) + j;
+        const int d = row >> 3, se = (row & 7) >> 1, a = row & 1;
+        const int ch = kk >> 3, te = (kk & 7) >> 1, b = kk & 1;
+        float val = 0.f;
+        if (d < kOff) {
+            if (!adj) {  // W[d][0][ch][se][te], layer with co = 1
+                const long e = ((((long)d * co + 0) * ci + ch) * 4 + se) * 4 + te;
+                const float wr = w[2 * e], wi = w[2 * e + 1];
+                val = a == 0 ? (b == 0 ? wr : -wi) : (b == 0 ? wi : wr);
+            } else {     // conj(W[d][ch][0][te][se]), layer with ci = 1: rows (t = se), K (o = ch, s = te)
+                const long e = ((((long)d * co + ch) * ci + 0) * 4 + te) * 4 + se;
+                const float wr = w[2 * e], wi = w[2 * e + 1];
+                val = a == 0 ? (b == 0 ? wr : wi) : (b == 0 ? -wi : wr);
+            }
+        }
+        frag[idx] = (uint16_t)f2bf_rne(val);
+    }
+}
+
+struct WfArgs {
+    const uint32_t* in;   // [n][V][16][12]
+    uint32_t* Y;          // [n][81][V][12] BF16 pairs
+    const uint4* frag;
+    long V;
+    int nlogical;
+    TileGeo g;
+};
+
+__global__ __launch_bounds__(256) void k_nn_wf_gemm(const WfArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kCols * kLdk];
+    const int lb = xcd_block(a.nlogical);
+    if (lb < 0) return;
+    const int tile = lb % a.g.ntile, rhs = lb / a.g.ntile;
+    int org[4];
+    tile_origin(a.g, tile, org);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    {
+        const int sl = tid >> 2, q = tid & 3;
+        int cs[4];
+        local_coords(sl, org, cs);
+        const int site = site_of(a.g, cs);
+#pragma unroll
+        for (int pp = 0; pp < 4; pp++) {
+            const int i = q * 4 + pp;
+            const uint4* ip = (const uint4*)(a.in + (((size_t)rhs * a.V + site) * 16 + i) * 12);
+            uint32_t w[12];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const uint4 v = ip[k];
+                w[4 * k] = v.x;
+                w[4 * k + 1] = v.y;
+                w[4 * k + 2] = v.z;
+                w[4 * k + 3] = v.w;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                *(uint4*)&lds[(sl * 3 + c) * kLdk + i * 8] = make_uint4(w[c], w[3 + c], w[6 + c], w[9 + c]);
+        }
+    }
+    __syncthreads();
+    uint32_t* Yr = a.Y + (size_t)rhs * kOff * a.V * 12;
+    for (int pass = 0; pass * 8 < kWfRowTiles; pass++) {
+        f32x4 acc[2][12];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int rt0 = pass * 8 + wv * 2;
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            bf16x8 af[2];
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const int rt = rt0 + r;
+                af[r] = rt < kWfRowTiles ? __builtin_bit_cast(bf16x8, a.frag[((size_t)rt * 4 + ks) * 64 + lane])
+                                         : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+            }
+            const int kb = ks * 32 + 8 * (lane >> 4);
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const int col = c * 16 + (lane & 15);
+                const bf16x8 bfr = __builtin_bit_cast(bf16x8, *(const uint4*)&lds[col * kLdk + kb]);
+#pragma unroll
+                for (int r = 0; r < 2; r++) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfr, acc[r][c], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int row0 = (rt0 + r) * 16 + 4 * (lane >> 4);
+            if (row0 >= kWfRows) continue;
+            const int d = row0 >> 3, s0 = (row0 & 7) >> 1;
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const int col = c * 16 + (lane & 15);
+                const int sl2 = col / 3, cc = col - 3 * (col / 3);
+                int c2[4];
+                local_coords(sl2, org, c2);
+                uint32_t* yp = Yr + ((size_t)d * a.V + site_of(a.g, c2)) * 12;
+                const f32x4 v = acc[r][c];
+                yp[s0 * 3 + cc] = pk2(v[0], v[1]);
+                yp[(s0 + 1) * 3 + cc] = pk2(v[2], v[3]);
+            }
+        }
+    }
+}
+
+// out(x) = sum_d M_d(x) Y_d(x + sgn d): one thread per (site, rhs), FP32 output [n][V][12]
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_nn_wf_gather(const uint32_t* __restrict__ Y, const uint2* __restrict__ ttab,
+                                                      float2* __restrict__ out, long V, int n, TileGeo g) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const int rhs = (int)(j / V);
+        const int x = (int)(j - (long)rhs * V);
+        int c[4];
+        {
+            int r = x;
+            c[0] = r % g.L[0];
+            r /= g.L[0];
+            c[1] = r % g.L[1];
+            r /= g.L[1];
+            c[2] = r % g.L[2];
+            c[3] = r / g.L[2];
+        }
+        float re[12], im[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) re[k] = im[k] = 0.f;
+        const uint32_t* Yr = Y + (size_t)rhs * kOff * V * 12;
+        for (int d = 0; d < kOff; d++) {
+            const int z = shifted_site(g, c, d, ADJ ? -1 : 1);
+            const uint2* tp = ttab + ((size_t)d * V + (ADJ ? z : x)) * 9;
+            uint2 T[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++) T[k] = tp[k];
+            const uint4* yp = (const uint4*)(Yr + ((size_t)d * V + z) * 12);
+            uint32_t y[12];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const uint4 v = yp[k];
+                y[4 * k] = v.x;
+                y[4 * k + 1] = v.y;
+                y[4 * k + 2] = v.z;
+                y[4 * k + 3] = v.w;
+            }
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+                for (int aa = 0; aa < 3; aa++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++) {
+                        const uint2 t = T[ADJ ? b * 3 + aa : aa * 3 + b];
+                        const uint32_t wa = ADJ ? (t.x ^ 0x80000000u) : t.x;
+                        const uint32_t wb = ADJ ? (t.y ^ 0x00008000u) : t.y;
+                        re[sp * 3 + aa] = dot2(wa, y[sp * 3 + b], re[sp * 3 + aa]);
+                        im[sp * 3 + aa] = dot2(wb, y[sp * 3 + b], im[sp * 3 + aa]);
+                    }
+        }
+        float2* op = out + ((size_t)rhs * V + x) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; k++) op[k] = make_float2(re[k], im[k]);
+    }
+}
+
 // ------------------------------------------------------------------ weight gradients
 struct DwArgs {
     const uint32_t* act;  // layer input [n][V][CI][12]
@@ -714,6 +897,8 @@ struct disco_net {
     uint2* ttab = nullptr;
     uint16_t* ffwd[3] = {nullptr, nullptr, nullptr};
     uint16_t* fadj[3] = {nullptr, nullptr, nullptr};
+    uint16_t* fwf_out = nullptr;   // weights-first fragments: last layer (forward)
+    uint16_t* fwf_in = nullptr;    // and the first layer's adjoint
     bool frags_ok = false;
     TileGeo geo;
     // activation workspaces (grow-only)
@@ -749,8 +934,34 @@ void net_frags(disco_net* net) {
         hipLaunchKernelGGL(k_nn_frag, dim3(gridfor(na)), dim3(256), 0, st, net->w + net->loff[l], net->lci[l],
                            net->lco[l], 1, net->fadj[l], na);
     }
+    const long nwf = (long)kWfRowTiles * 4 * 64 * 8;
+    hipLaunchKernelGGL(k_nn_wf_frag, dim3(gridfor(nwf)), dim3(256), 0, st, net->w + net->loff[2], net->lci[2],
+                       net->lco[2], 0, net->fwf_out);
+    hipLaunchKernelGGL(k_nn_wf_frag, dim3(gridfor(nwf)), dim3(256), 0, st, net->w + net->loff[0], net->lci[0],
+                       net->lco[0], 1, net->fwf_in);
     HIPCHK(hipGetLastError());
     net->frags_ok = true;
+}
+
+// weights-first one-channel layer: forward last layer (ADJ false) or adjoint of
+// the first layer (ADJ true); in [n][V][16][12] BF16, out FP32 [n][V][12]
+template <bool ADJ>
+void wf_launch(disco_net* net, int n, const uint32_t* in, float2* out) {
+    disco_ctx* ctx = net->ctx;
+    const long V = ctx->V;
+    uint32_t* Y = (uint32_t*)net_ws(net, "wf_Y", sizeof(uint32_t) * (size_t)n * kOff * V * 12);
+    WfArgs a;
+    a.in = in;
+    a.Y = Y;
+    a.frag = (const uint4*)(ADJ ? net->fwf_in : net->fwf_out);
+    a.V = V;
+    a.g = net->geo;
+    a.nlogical = net->geo.ntile * n;
+    const int prof = prof_begin(ctx, 20);
+    hipLaunchKernelGGL(k_nn_wf_gemm, dim3(xcd_grid(a.nlogical)), dim3(256), 0, ctx->stream, a);
+    hipLaunchKernelGGL((k_nn_wf_gather<ADJ>), dim3(gridfor(V * n)), dim3(256), 0, ctx->stream, Y, net->ttab, out, V, n,
+                       net->geo);
+    if (prof >= 0) prof_end(ctx, prof, DISCO_KERNEL_NN, 2.0 * 8 * 128 * kOff * 3.0 * (double)V * n);
 }
 
 template <int CI, int CO, bool ADJ, bool OUT32>
@@ -777,7 +988,7 @@ void net_forward(disco_net* net, int n, const uint32_t* act0, uint32_t* act1, ui
     net_frags(net);
     layer_launch<1, 16, false, false>(net, n, act0, act1, net->ffwd[0]);
     layer_launch<16, 16, false, false>(net, n, act1, act2, net->ffwd[1]);
-    layer_launch<16, 1, false, true>(net, n, act2, out, net->ffwd[2]);
+    wf_launch<false>(net, n, act2, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -814,7 +1025,7 @@ void net_backward(disco_net* net, int n, const uint32_t* act0, const uint32_t* a
     dw_launch<16, 16>(net, n, act1, g2, net->gw + net->loff[1]);
     layer_launch<16, 16, true, false>(net, n, g2, g1, net->fadj[1]);
     dw_launch<1, 16>(net, n, act0, g1, net->gw + net->loff[0]);
-    if (g0) layer_launch<16, 1, true, true>(net, n, g1, g0, net->fadj[0]);
+    if (g0) wf_launch<true>(net, n, g1, g0);
     HIPCHK(hipGetLastError());
 }
 
@@ -881,6 +1092,8 @@ extern "C" int disco_net_create(disco_ctx* ctx, int channels, unsigned long long
             HIPCHK(hipMalloc(&net->ffwd[l], sizeof(uint16_t) * frag_elems(net->lci[l], net->lco[l])));
             HIPCHK(hipMalloc(&net->fadj[l], sizeof(uint16_t) * frag_elems(net->lco[l], net->lci[l])));
         }
+        HIPCHK(hipMalloc(&net->fwf_out, sizeof(uint16_t) * (size_t)kWfRowTiles * 4 * 64 * 8));
+        HIPCHK(hipMalloc(&net->fwf_in, sizeof(uint16_t) * (size_t)kWfRowTiles * 4 * 64 * 8));
         // start: identity through channel 0 of every layer plus small Gaussian noise
         std::vector<float> h(net->nw);
         std::mt19937_64 rng(seed);
@@ -921,7 +1134,8 @@ extern "C" int disco_net_destroy(disco_net* net) {
         if (net->ffwd[l]) (void)hipFree(net->ffwd[l]);
         if (net->fadj[l]) (void)hipFree(net->fadj[l]);
     }
-    for (void* p : {(void*)net->w, (void*)net->gw, (void*)net->am, (void*)net->av, (void*)net->ttab})
+    for (void* p : {(void*)net->w, (void*)net->gw, (void*)net->am, (void*)net->av, (void*)net->ttab,
+                    (void*)net->fwf_out, (void*)net->fwf_in})
         if (p) (void)hipFree(p);
     delete net;
     return DISCO_OK;
