@@ -240,7 +240,10 @@ __device__ __forceinline__ void rhs_partials(const double (&v)[2 * NQ], int n, i
 // host-side declarations of internal entry points used across units
 namespace disco {
 // stencil on native blocks; epilogue flags below; part may be null when no reduction is asked
-enum Epi { EPI_NONE = 0, EPI_RESID = 1, EPI_DOTAUX = 2, EPI_NORM = 4, EPI_DOTIN = 8 };
+// reductions, in this order of their partial-sum slots: DOTAUX <aux2, out>,
+// NORM ||out||^2, DOTIN <out, in>, DOTAUXIN <aux2, in> (in = the operand the
+// site-local term acts on: the input, or aux in even-odd mode)
+enum Epi { EPI_NONE = 0, EPI_RESID = 1, EPI_DOTAUX = 2, EPI_NORM = 4, EPI_DOTIN = 8, EPI_DOTAUXIN = 16 };
 struct StencilCall {
     int prec;             // DISCO_F64/F32/BF16
     int dagger;
@@ -248,7 +251,7 @@ struct StencilCall {
     const void* in;
     void* out;
     const void* aux;      // b for EPI_RESID
-    const void* aux2;     // w for EPI_DOTAUX
+    const void* aux2;     // w for EPI_DOTAUX / EPI_DOTAUXIN
     const uint8_t* mask;  // null = full operator
     double2* part;        // partial sums [r][nq][nsb]
     int epi;

@@ -174,22 +174,24 @@ __global__ void k_bicg_s(const void* r_, const void* v_, void* s_, VecGeo g, con
     }
 }
 
-// x += alpha p + omega s ; r = s - omega t ; partials <rhat, r>, ||r||^2
+// Fused end of a BiCGStab iteration, once omega and beta are known:
+//   x += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v) ;
+//   partial ||r||^2 of the stored (rounded) residual
 template <class IO>
-__global__ void k_bicg_xr(void* x_, const void* p_, const void* s_, const void* t_, void* r_, const void* rh_, VecGeo g,
-                          const RhsScal* sc, double2* part) {
+__global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, const void* v_, void* r_, VecGeo g,
+                           const RhsScal* sc, double2* part) {
     typedef Unit<IO> U;
     typedef typename IO::T T;
     const int rr = threadIdx.x % g.n;
-    const cx<T> al = cast<T>(sc[rr].alpha), om = cast<T>(sc[rr].omega);
-    double acc[4] = {0, 0, 0, 0};
+    const cx<T> al = cast<T>(sc[rr].alpha), om = cast<T>(sc[rr].omega), be = cast<T>(sc[rr].beta);
+    double acc[2] = {0, 0};
     VEC_LOOP(g) {
-        cx<T> x[U::C], p[U::C], s[U::C], t[U::C], rh[U::C], rn[U::C];
+        cx<T> x[U::C], p[U::C], s[U::C], t[U::C], v[U::C], rn[U::C];
         U::ld(x_, i, x);
         U::ld(p_, i, p);
         U::ld(s_, i, s);
         U::ld(t_, i, t);
-        U::ld(rh_, i, rh);
+        U::ld(v_, i, v);
 #pragma unroll
         for (int c = 0; c < U::C; c++) {
             x[c] = x[c] + al * p[c] + om * s[c];
@@ -197,34 +199,15 @@ __global__ void k_bicg_xr(void* x_, const void* p_, const void* s_, const void* 
         }
         U::st(x_, i, x);
         U::st(r_, i, rn);
-        U::ld(r_, i, rn);  // reductions on the stored (rounded) residual
+        U::ld(r_, i, rn);  // the stored (rounded) residual feeds p and the norm
 #pragma unroll
         for (int c = 0; c < U::C; c++) {
-            cx<T> d = cjmul(rh[c], rn[c]);
-            acc[0] += (double)d.re;
-            acc[1] += (double)d.im;
-            acc[2] += (double)nrm(rn[c]);
+            p[c] = rn[c] + be * (p[c] - om * v[c]);
+            acc[0] += (double)nrm(rn[c]);
         }
-    }
-    rhs_partials<2>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
-}
-
-// p = r + beta (p - omega v)
-template <class IO>
-__global__ void k_bicg_p(void* p_, const void* r_, const void* v_, VecGeo g, const RhsScal* sc) {
-    typedef Unit<IO> U;
-    typedef typename IO::T T;
-    const int rr = threadIdx.x % g.n;
-    const cx<T> be = cast<T>(sc[rr].beta), om = cast<T>(sc[rr].omega);
-    VEC_LOOP(g) {
-        cx<T> p[U::C], r[U::C], v[U::C];
-        U::ld(p_, i, p);
-        U::ld(r_, i, r);
-        U::ld(v_, i, v);
-#pragma unroll
-        for (int c = 0; c < U::C; c++) p[c] = r[c] + be * (p[c] - om * v[c]);
         U::st(p_, i, p);
     }
+    rhs_partials<1>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
 }
 
 // ---- CGNR vector steps (FP64)
@@ -326,46 +309,42 @@ __global__ void k_sc_bicg_alpha(const double2* part, int nparts, RhsScal* sc) {
     s.alpha = s.active ? cdiv(s.rho, q[0]) : mk(0.0, 0.0);
 }
 
-// partials ||t||^2, <t, s> -> omega
-__global__ void k_sc_bicg_omega(const double2* part, int nparts, RhsScal* sc) {
-    cd q[2];
-    fold<2>(part, blockIdx.x, nparts, q);
+// partials <rhat, t>, ||t||^2, <t, s>, <rhat, s> of the second operator
+// application -> omega, and with it the next rho = <rhat, s - omega t> and beta
+// (the fused iteration: no separate pass over r for <rhat, r>)
+__global__ void k_sc_bicg_omega_beta(const double2* part, int nparts, RhsScal* sc) {
+    cd q[4];
+    fold<4>(part, blockIdx.x, nparts, q);
     if (threadIdx.x) return;
     RhsScal& s = sc[blockIdx.x];
-    if (s.active && !(q[0].re > 0)) {
+    if (s.active && !(q[1].re > 0)) {
         s.active = 0;
         s.breakdown = 1;
     }
-    s.omega = s.active ? mk(q[1].re / q[0].re, q[1].im / q[0].re) : mk(0.0, 0.0);
-    if (s.active && nrm(s.omega) == 0.0) {
+    s.omega = s.active ? mk(q[2].re / q[1].re, q[2].im / q[1].re) : mk(0.0, 0.0);
+    if (s.active && (nrm(s.omega) == 0.0 || nrm(s.rho) == 0.0)) {
         s.active = 0;
         s.breakdown = 1;
         s.omega = mk(0.0, 0.0);
     }
-}
-
-// partials <rhat, r>, ||r||^2 -> beta; convergence relative to the inner start
-__global__ void k_sc_bicg_beta(const double2* part, int nparts, RhsScal* sc, double tol2) {
-    cd q[2];
-    fold<2>(part, blockIdx.x, nparts, q);
-    if (threadIdx.x) return;
-    RhsScal& s = sc[blockIdx.x];
     if (!s.active) {
         s.beta = mk(0.0, 0.0);
         return;
     }
-    s.irr = q[1].re;
-    cd rho_new = q[0];
-    if (nrm(s.rho) == 0.0) {
-        s.active = 0;
-        s.breakdown = 1;
-        s.beta = mk(0.0, 0.0);
-        return;
-    }
+    const cd rho_new = q[3] - s.omega * q[0];
     s.beta = cdiv(rho_new, s.rho) * cdiv(s.alpha, s.omega);
     s.rho = rho_new;
+}
+
+// partial ||r||^2 -> inner convergence relative to the inner start
+__global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, double tol2) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    if (!s.active) return;
+    s.irr = q[0].re;
     if (s.irr <= tol2 * s.ibb) s.active = 0;
-    if (!s.active) s.beta = mk(0.0, 0.0);
 }
 
 // CGNR: mode 0 init gam = ||z||^2 ; mode 1 alpha = gam / ||w||^2 ; mode 2 rr = ||r||^2 ;
@@ -548,16 +527,18 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
     norm2<IO>(w, r, g);
     k_sc_bicg_init<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc);
     const double tol2 = inner_tol * inner_tol;
-    // one BiCGStab iteration: 2 operator applications with fused reductions, 3 vector updates, 3 scalar steps
+    // one BiCGStab iteration: 2 operator applications with fused reductions
+    // (the second one's four sums give omega and beta), 2 vector passes
+    // (s, then x, r and p together), 3 scalar steps
     auto iteration = [&]() {
         op_apply(w, op, prec, p, v, rh, mask, disco::EPI_DOTAUX, tmp);
         k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
-        op_apply(w, op, prec, s, t, nullptr, mask, disco::EPI_NORM | disco::EPI_DOTIN, tmp);
-        k_sc_bicg_omega<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
-        hipLaunchKernelGGL(k_bicg_xr<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, r, rh, g, w.sc, w.part);
-        k_sc_bicg_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
-        hipLaunchKernelGGL(k_bicg_p<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, r, v, g, w.sc);
+        op_apply(w, op, prec, s, t, rh, mask,
+                 disco::EPI_DOTAUX | disco::EPI_NORM | disco::EPI_DOTIN | disco::EPI_DOTAUXIN, tmp);
+        k_sc_bicg_omega_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
+        hipLaunchKernelGGL(k_bicg_xrp<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, v, r, g, w.sc, w.part);
+        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
     };
     // A chunk of check_every iterations is captured once as a graph and replayed
     // between the host's convergence reads (eager when profiling or disabled).
@@ -1161,7 +1142,7 @@ extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inne
             w.nsb = disco::stencil_nsb(ctx, n);
             w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
             VecGeo g = vgeo(ctx->V, DISCO_F64, n);
-            w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * (size_t)std::max(w.nsb, g.nb) * 3 * n);
+            w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * (size_t)std::max(w.nsb, g.nb) * 4 * n);
             HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
             double2* b64 = (double2*)ws_get(ctx, "tune_b", disco::native_bytes(ctx, DISCO_F64, n));
             void* rin = ws_get(ctx, "dc_rin", disco::native_bytes(ctx, inner_prec, n));

@@ -44,7 +44,7 @@ struct StencilArgs {
     long V;        // lattice sites (stride of the link and clover planes)
     long Vv;       // sites of the spinor vectors (V, or V/2 in even-odd mode)
     int nsites;    // sites visited by the launch (entries of trav)
-    int eo_aux;    // even-odd mode: read aux at the site (ca, cg or DOTIN need it)
+    int eo_aux;    // even-odd mode: read aux at the site (ca, cg, DOTIN or DOTAUXIN need it)
     double ca, cg, cb;
     int L[4];
     long st[4];
@@ -228,7 +228,7 @@ __device__ __forceinline__ void hops(const StencilArgs& a, int s, const int* x, 
 template <int EPI>
 struct EpiCount {
     static constexpr int nq = ((EPI & disco::EPI_DOTAUX) ? 1 : 0) + ((EPI & disco::EPI_NORM) ? 1 : 0) +
-                              ((EPI & disco::EPI_DOTIN) ? 1 : 0);
+                              ((EPI & disco::EPI_DOTIN) ? 1 : 0) + ((EPI & disco::EPI_DOTAUXIN) ? 1 : 0);
 };
 
 // With STAGE (FP32 links and clover, at most kStageSites sites per block) the
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
             for (int k = 0; k < 12; k++) p[k] = mk(fma(cb, acc[k].re, cg * pin[k].re), fma(cb, acc[k].im, cg * pin[k].im));
         } else {
             IO::template loadv<BUF>(a.in, Vv, n, r, sv, p);
-            if (EPI & disco::EPI_DOTIN) {
+            if (EPI & (disco::EPI_DOTIN | disco::EPI_DOTAUXIN)) {
 #pragma unroll
                 for (int k = 0; k < 12; k++) pin[k] = p[k];
             }
@@ -370,9 +370,9 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         }
         IO::store(a.out, Vv, n, r, sv, o);
         int q = 0;
+        cx<T> w[12];
+        if (EPI & (disco::EPI_DOTAUX | disco::EPI_DOTAUXIN)) IO::template loadv<BUF>(a.aux2, Vv, n, r, sv, w);
         if (EPI & disco::EPI_DOTAUX) {
-            cx<T> w[12];
-            IO::template loadv<BUF>(a.aux2, Vv, n, r, sv, w);
             double re = 0, im = 0;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
@@ -396,6 +396,18 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 cx<T> d = cjmul(o[k], pin[k]);
+                re += (double)d.re;
+                im += (double)d.im;
+            }
+            red[2 * q] = re;
+            red[2 * q + 1] = im;
+            q++;
+        }
+        if (EPI & disco::EPI_DOTAUXIN) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                cx<T> d = cjmul(w[k], pin[k]);
                 re += (double)d.re;
                 im += (double)d.im;
             }
@@ -466,6 +478,9 @@ void launch_epi(disco_ctx* ctx, const StencilArgs& a, int epi, bool eo) {
             case EPI_NONE: launch_one<IO, EPI_NONE, true>(ctx, a); break;
             case EPI_DOTAUX: launch_one<IO, EPI_DOTAUX, true>(ctx, a); break;
             case EPI_NORM | EPI_DOTIN: launch_one<IO, EPI_NORM | EPI_DOTIN, true>(ctx, a); break;
+            case EPI_DOTAUX | EPI_NORM | EPI_DOTIN | EPI_DOTAUXIN:
+                launch_one<IO, EPI_DOTAUX | EPI_NORM | EPI_DOTIN | EPI_DOTAUXIN, true>(ctx, a);
+                break;
             default: disco_throw(DISCO_EINVAL, "even-odd stencil epilogue %d not built", epi);
         }
         return;
@@ -475,6 +490,9 @@ void launch_epi(disco_ctx* ctx, const StencilArgs& a, int epi, bool eo) {
         case EPI_DOTAUX: launch_one<IO, EPI_DOTAUX, false>(ctx, a); break;
         case EPI_NORM: launch_one<IO, EPI_NORM, false>(ctx, a); break;
         case EPI_NORM | EPI_DOTIN: launch_one<IO, EPI_NORM | EPI_DOTIN, false>(ctx, a); break;
+        case EPI_DOTAUX | EPI_NORM | EPI_DOTIN | EPI_DOTAUXIN:
+            launch_one<IO, EPI_DOTAUX | EPI_NORM | EPI_DOTIN | EPI_DOTAUXIN, false>(ctx, a);
+            break;
         case EPI_RESID | EPI_NORM: launch_one<IO, EPI_RESID | EPI_NORM, false>(ctx, a); break;
         case EPI_RESID: launch_one<IO, EPI_RESID, false>(ctx, a); break;
         default: disco_throw(DISCO_EINVAL, "stencil epilogue %d not built", epi);
@@ -486,7 +504,8 @@ void launch_epi(disco_ctx* ctx, const StencilArgs& a, int epi, bool eo) {
 namespace disco {
 
 int nq_of(int epi) {
-    return ((epi & EPI_DOTAUX) ? 1 : 0) + ((epi & EPI_NORM) ? 1 : 0) + ((epi & EPI_DOTIN) ? 1 : 0);
+    return ((epi & EPI_DOTAUX) ? 1 : 0) + ((epi & EPI_NORM) ? 1 : 0) + ((epi & EPI_DOTIN) ? 1 : 0) +
+           ((epi & EPI_DOTAUXIN) ? 1 : 0);
 }
 
 int stencil_spb(int n) { return n >= kStencilBlock ? 1 : kStencilBlock / n; }
@@ -574,7 +593,7 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     a.V = ctx->V;
     a.Vv = eo ? ctx->V / 2 : ctx->V;
     a.nsites = (int)a.Vv;
-    a.eo_aux = eo && (c.ca != 0.0 || c.cg != 0.0 || (c.epi & EPI_DOTIN)) ? 1 : 0;
+    a.eo_aux = eo && (c.ca != 0.0 || c.cg != 0.0 || (c.epi & (EPI_DOTIN | EPI_DOTAUXIN))) ? 1 : 0;
     a.ca = c.ca;
     a.cg = c.cg;
     a.cb = c.cb;
@@ -594,7 +613,7 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     a.stage = ctx->opt_stage == 1 || (ctx->opt_stage == -1 && c.nrhs >= 16);
     double sp = c.prec == DISCO_F64 ? 8 : c.prec == DISCO_F32 ? 4 : 2;  // bytes per spinor real
     double sg = c.prec == DISCO_F64 ? 8 : 4;                             // bytes per link/clover real
-    int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & EPI_DOTAUX) ? 1 : 0) + (a.eo_aux ? 1 : 0);
+    int nvec = 2 + ((c.epi & EPI_RESID) ? 1 : 0) + ((c.epi & (EPI_DOTAUX | EPI_DOTAUXIN)) ? 1 : 0) + (a.eo_aux ? 1 : 0);
     // each spinor once, every link of the sites visited (all 4V links in even-odd
     // mode, where the backward links belong to the other parity), clover once
     double bytes = eo ? (double)a.Vv * (c.nrhs * nvec * 24 * sp + 144 * sg + 72 * sg + (c.mask ? 1 : 0))
