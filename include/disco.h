@@ -138,7 +138,10 @@ int disco_dirac_block_apply(disco_ctx* ctx, const disco_domains* dom, int prec, 
  *   F64  : [12][V][nrhs] complex double, plane k = spin*3 + colour
  *   F32  : [6][V][nrhs]  float4 = components (2p, 2p+1) as (re, im, re, im)
  *   BF16 : [3][V][nrhs]  16 bytes = components 4q..4q+3 as bf16 (re, im) pairs
- * disco_native_bytes gives the size of an nrhs block (nrhs <= 256 per call). */
+ * disco_native_bytes gives the size of an nrhs block (nrhs <= 256 per call).
+ * disco_dirac_apply_native takes at most min(256, (2^32 - 1) / (16 V)) right-
+ * hand sides per call (one plane, V * nrhs * 16 bytes, must stay below 4 GiB),
+ * else it fails with DISCO_EINVAL. */
 long long disco_native_bytes(const disco_ctx* ctx, int prec, int nrhs);
 int disco_to_native(disco_ctx* ctx, int prec, int nrhs, const void* in_canonical, void* out_native);
 int disco_from_native(disco_ctx* ctx, int prec, int nrhs, const void* in_native, void* out_canonical);
@@ -170,7 +173,8 @@ typedef struct {
     int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */
     double inner_tol;  /* relative reduction asked of each inner solve (e.g. 1e-5) */
     int rhs_block;     /* right-hand sides per batched launch; 0 = the autotuned block for
-                        * inner_prec if disco_autotune ran, else 16 */
+                        * inner_prec if disco_autotune ran, else 16; clamped to 64 and to
+                        * the plane limit given under disco_autotune */
     int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
     int check_every;   /* iterations between host convergence checks (0 = default: 2 for
                         * BICGSTAB_DC, whose inner solves first run, without checks, as many
@@ -327,7 +331,10 @@ int disco_effective_mass(const double* C, int n, double* meff);
  * 4, 8, 16 and 32 on device-generated random sources, and keep the block with
  * the lowest cost per right-hand side and iteration for later solves with
  * rhs_block = 0.  best (host) receives it; cost_us (host, 4 entries, may be
- * NULL) the measured microseconds per right-hand side and iteration. */
+ * NULL) the measured microseconds per right-hand side and iteration, 0 for a
+ * block not tried.  A block is tried only if one spinor plane of it
+ * (V * block * 16 bytes at every precision) stays below 4 GiB, the limit of
+ * the stencil's 32-bit offsets; solves clamp rhs_block to the same limit. */
 int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int* best, double* cost_us);
 
 /* ---------------------------------------------------------------- learned preconditioner

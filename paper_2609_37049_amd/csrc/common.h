@@ -261,7 +261,11 @@ struct StencilCall {
     double ca = 0, cg = 0, cb = 0;
 };
 int nq_of(int epi);
-int stencil_nsb(disco_ctx* ctx, int n, bool eo = false);   // partial-sum slots per (rhs, quantity)
+int stencil_nsb(disco_ctx* ctx, int n, bool eo = false);
+// right-hand sides a stencil launch can address (32-bit offsets within a spinor plane)
+int plane_rhs_limit(const disco_ctx* ctx);
+// largest block of a batched solve: 64 and the plane limit
+int max_rhs_block(const disco_ctx* ctx);   // partial-sum slots per (rhs, quantity)
 bool eo_supported(const disco_ctx* ctx);
 int stencil_spb(int n);                    // sites per stencil block
 void build_traversal(disco_ctx* ctx);

@@ -1103,8 +1103,11 @@ int default_rhs_block(const disco_solver_params& P, int nrhs, const disco_ctx* c
     if (b <= 0 && ctx && P.method == DISCO_BICGSTAB_DC && P.inner_prec >= 0 && P.inner_prec <= 2)
         b = ctx->tuned_block[P.inner_prec];
     if (b <= 0) b = 16;
-    return std::max(1, std::min({b, nrhs, 64}));
+    return std::max(1, std::min({b, nrhs, 64, max_rhs_block(ctx)}));
 }
+
+// Largest solver block: 64, and no more than the stencil's plane limit.
+int max_rhs_block(const disco_ctx* ctx) { return ctx ? std::min(64, plane_rhs_limit(ctx)) : 64; }
 
 }  // namespace disco
 
@@ -1129,12 +1132,13 @@ extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inne
         activate(ctx);
         const int cand[4] = {4, 8, 16, 32};
         const int iters = 20;
-        double cost[4];
+        double cost[4] = {0, 0, 0, 0};
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         for (int c = 0; c < 4; c++) {
             const int n = cand[c];
+            if (n > disco::max_rhs_block(ctx)) continue;
             Work w;
             w.ctx = ctx;
             w.n = n;
@@ -1173,7 +1177,7 @@ extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inne
         (void)hipEventDestroy(e1);
         int bi = 0;
         for (int c = 1; c < 4; c++)
-            if (cost[c] < cost[bi]) bi = c;
+            if (cost[c] > 0 && cost[c] < cost[bi]) bi = c;
         ctx->tuned_block[inner_prec] = cand[bi];
         if (best) *best = cand[bi];
         if (cost_us)

@@ -510,6 +510,12 @@ int nq_of(int epi) {
 
 int stencil_spb(int n) { return n >= kStencilBlock ? 1 : kStencilBlock / n; }
 
+// Right-hand sides whose spinor planes (V n 16 bytes each, at every precision)
+// stay below 4 GiB: the stencil addresses a plane with 32-bit offsets.
+int plane_rhs_limit(const disco_ctx* ctx) {
+    return (int)std::max(1LL, std::min((long long)kStencilBlock, ((1LL << 32) - 1) / (16LL * ctx->V)));
+}
+
 // Site order of the stencil.  Each XCD (8 contiguous ranges of the order)
 // takes one slab of Lt/8 timeslices when Lt is a multiple of 8.  Inside a slab
 // the order is x fastest, then y within a tile of yt rows, then t within the
@@ -576,6 +582,9 @@ int stencil_nsb(disco_ctx* ctx, int n, bool eo) {
 void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     REQUIRE(ctx->have_clover, DISCO_ESTATE, "operator applied before clover_setup");
     REQUIRE(c.nrhs >= 1 && c.nrhs <= kStencilBlock, DISCO_EINVAL, "nrhs per launch must be in 1..%d", kStencilBlock);
+    REQUIRE(c.nrhs <= plane_rhs_limit(ctx), DISCO_EINVAL,
+            "%d right-hand sides per launch exceed the %d that 32-bit plane offsets address at this volume", c.nrhs,
+            plane_rhs_limit(ctx));
     REQUIRE(!(c.dagger && (c.epi & EPI_DOTIN)), DISCO_EINVAL, "DOTIN epilogue with dagger");
     const bool eo = c.eo_target >= 0;
     REQUIRE(!eo || (eo_supported(ctx) && c.eo_target <= 1 && !c.dagger && !(c.epi & EPI_RESID)), DISCO_EINVAL,
@@ -722,8 +731,9 @@ static int apply_canonical(disco_ctx* ctx, const disco_domains* dom, int prec, i
         activate(ctx);
         if (nrhs == 0) return;
         const size_t field = (size_t)ctx->V * 12 * sizeof(double2);
-        for (int r0 = 0; r0 < nrhs; r0 += 64) {
-            const int n = std::min(64, nrhs - r0);
+        const int cap = std::min(64, disco::plane_rhs_limit(ctx));
+        for (int r0 = 0; r0 < nrhs; r0 += cap) {
+            const int n = std::min(cap, nrhs - r0);
             size_t nb = disco::native_bytes(ctx, prec, n);
             void* a = ws_get(ctx, "apply_in", nb);
             void* b = ws_get(ctx, "apply_out", nb);

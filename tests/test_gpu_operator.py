@@ -183,3 +183,29 @@ def test_full_size_precision_workload_operator(disco):
         assert _rel(out[sample], ref) < tol
         outb = ctx.dirac_block_apply(dom, t, p).cpu().numpy()
         assert _rel(outb[sample], refb) < tol
+
+
+def test_native_apply_plane_offset_limit(disco):
+    """At V = 32^4 one spinor plane of 256 right-hand sides is V * 256 * 16 bytes
+    = 4 GiB, beyond the stencil's 32-bit plane offsets: the call must fail with
+    EINVAL before any launch.  255 right-hand sides (just below 4 GiB, the
+    non-descriptor load path) run, and D 0 = 0."""
+    import torch
+    dims = (32, 32, 32, 32)
+    V = int(np.prod(dims))
+    ctx = disco.Context(dims, BC)
+    U = np.broadcast_to(np.eye(3, dtype=np.complex128), (V, 4, 3, 3)).copy()
+    ctx.gauge_set(U)
+    ctx.clover_setup(0.12, 1.0)
+    nb = ctx.native_bytes(disco.BF16, 256)
+    x = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.dirac_apply_native(None, disco.BF16, x, y, 256)
+    assert e.value.code == disco.EINVAL
+    n = 255
+    nb = ctx.native_bytes(disco.BF16, n)
+    y.view(torch.int32).fill_(-1)
+    ctx.dirac_apply_native(None, disco.BF16, x[:nb], y[:nb], n)
+    torch.cuda.synchronize()
+    assert int(y[:nb].count_nonzero()) == 0
