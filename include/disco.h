@@ -72,8 +72,14 @@ enum { DISCO_G_1 = 0, DISCO_G_5 = 1, DISCO_G_X = 2, DISCO_G_Y = 3, DISCO_G_Z = 4
 enum {
     DISCO_CGNR_F64 = 0,    /* conjugate gradients on D^+ D, all FP64 (plain judge) */
     DISCO_BICGSTAB_DC = 1, /* BiCGStab in inner_prec inside FP64 defect correction */
-    DISCO_FGMRES_NN = 2    /* flexible GMRES(restart), FP32 Krylov basis, preconditioned by a
+    DISCO_FGMRES_NN = 2,   /* flexible GMRES(restart), FP32 Krylov basis, preconditioned by a
                             * trained network (params.net), inside FP64 defect correction */
+    DISCO_BICGSTAB_RU = 3  /* BiCGStab in inner_prec with reliable updates: one Krylov process
+                            * for the whole solve; whenever a recursive residual has fallen by
+                            * inner_tol (default 3e-2 for BF16, 1e-3 for FP32) the corrections
+                            * are folded into the FP64 solution, the FP64 true residual replaces
+                            * the recursive one and the process continues (lanes that break
+                            * down or stall restart it); even-odd as for BICGSTAB_DC */
 };
 
 /* ---------------------------------------------------------------- context */
@@ -167,7 +173,7 @@ int disco_set_option(disco_ctx* ctx, int option, int value);
 
 /* ---------------------------------------------------------------- solver */
 typedef struct {
-    int method;        /* DISCO_CGNR_F64 or DISCO_BICGSTAB_DC */
+    int method;        /* DISCO_CGNR_F64, DISCO_BICGSTAB_DC, DISCO_FGMRES_NN, DISCO_BICGSTAB_RU */
     double tol;        /* target true ||b - D x|| / ||b|| per right-hand side, FP64 */
     int max_iter;      /* cap on inner iterations summed over outer cycles */
     int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -
 F64, F32, BF16 = 0, 1, 2
 HOST, DEVICE = 0, 1
 G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
-CGNR_F64, BICGSTAB_DC, FGMRES_NN = 0, 1, 2
+CGNR_F64, BICGSTAB_DC, FGMRES_NN, BICGSTAB_RU = 0, 1, 2, 3
 K_STENCIL = 0
 K_NN = 2
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <functional>
 
 #include "spinor_io.h"
 
@@ -37,7 +38,14 @@ struct RhsScal {
     cd rho, alpha, omega, beta;
     double rr, bb, irr, ibb, gam, scale;
     int active, breakdown, outer_done, pad;
+    double best;  // smallest inner ||r||^2 since it last halved (reliable updates)
+    int since;    // inner iterations since then
+    int pad2;
 };
+
+// inner iterations without a halving of a lane's inner residual before it
+// stops (its Krylov process then restarts)
+constexpr int kRuStall = 100;
 
 // --------------------------------------------------------------- vector units
 // One "unit" is the widest natural load of a storage format: 1 complex
@@ -130,12 +138,13 @@ __global__ void k_copy_scale(const void* src, void* dst, long V, int n, const Rh
 }
 
 // x64 += (1/scale[r]) * e (inner precision) for right-hand sides that ran
+// (not for finished ones, nor for inner solves that diverged)
 template <class IO>
 __global__ void k_dc_update(double2* x64, const void* e, long V, int n, const RhsScal* sc) {
     const long tot = V * n;
     for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
         const long s = j / n, r = j - s * n;
-        if (sc[r].outer_done) continue;
+        if (sc[r].outer_done || sc[r].breakdown == 2) continue;
         const double f = sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0;
         cx<typename IO::T> a[12];
         cx<double> x[12];
@@ -210,6 +219,54 @@ __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, c
     rhs_partials<1>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
 }
 
+// Reliable update of the inner BiCGStab (continued, not restarted): the
+// recursive residual r is replaced by rn, the residual of the inner system
+// recomputed from the FP64 true residual; p, built from the old r, takes the
+// same change (p += rn - r); the inner correction e restarts at 0.  Lanes
+// that broke down or stalled (and finished lanes) restart the Krylov process
+// instead: p = rhat = rn.  Partials <rhat, rn>, ||rn||^2.
+template <class IO>
+__global__ void k_ru_refresh(void* r_, const void* rn_, void* p_, void* rh_, void* e_, VecGeo g, const RhsScal* sc,
+                             double2* part) {
+    typedef Unit<IO> U;
+    typedef typename IO::T T;
+    const int rr = threadIdx.x % g.n;
+    const bool restart = sc[rr].breakdown || sc[rr].outer_done;
+    double acc[4] = {0, 0, 0, 0};
+    cx<T> z[U::C];
+#pragma unroll
+    for (int c = 0; c < U::C; c++) z[c] = mk((T)0, (T)0);
+    VEC_LOOP(g) {
+        cx<T> rn[U::C], r[U::C], p[U::C], rh[U::C];
+        U::ld(rn_, i, rn);
+        if (restart) {
+#pragma unroll
+            for (int c = 0; c < U::C; c++) {
+                p[c] = rn[c];
+                rh[c] = rn[c];
+            }
+            U::st(rh_, i, rh);
+        } else {
+            U::ld(r_, i, r);
+            U::ld(p_, i, p);
+            U::ld(rh_, i, rh);
+#pragma unroll
+            for (int c = 0; c < U::C; c++) p[c] = p[c] + (rn[c] - r[c]);
+        }
+        U::st(r_, i, rn);
+        U::st(p_, i, p);
+        U::st(e_, i, z);
+#pragma unroll
+        for (int c = 0; c < U::C; c++) {
+            cx<T> d = cjmul(rh[c], rn[c]);
+            acc[0] += (double)d.re;
+            acc[1] += (double)d.im;
+            acc[2] += (double)nrm(rn[c]);
+        }
+    }
+    rhs_partials<2>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
+}
+
 // ---- CGNR vector steps (FP64)
 // x += alpha p ; r -= alpha w ; partial ||r||^2
 __global__ void k_cgnr_xr(double2* x, const double2* p, const double2* w, double2* rv, VecGeo g, const RhsScal* sc,
@@ -265,6 +322,10 @@ __device__ __forceinline__ cd cdiv(cd a, cd b) {
 
 // mode 0: bb = rr = ||b||^2 (outer start); mode 1: rr = ||r||^2.  Then decide
 // outer convergence and set scale = 1/||r|| for the next defect.
+// mode 2 (reliable updates): rr = ||r||^2 with the scale of the start kept;
+// a lane whose inner residual reached its reduction while the true residual
+// fell by less than a factor 2 (in the squared norm) is marked for a Krylov
+// restart; gam keeps the previous update's ||r||^2.
 __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mode, double tol2) {
     cd q[1];
     fold<1>(part, blockIdx.x, nparts, q);
@@ -273,12 +334,37 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
     if (mode == 0) {
         s.bb = q[0].re;
         s.rr = q[0].re;
+        s.gam = q[0].re;
         s.outer_done = 0;
     } else {
         s.rr = q[0].re;
     }
+    if (mode == 2) {
+        if (!s.outer_done && !s.active && !s.breakdown && s.rr > 0.5 * s.gam) s.breakdown = 1;
+        s.gam = s.rr;
+        if (s.rr <= tol2 * s.bb) s.outer_done = 1;
+        if (s.outer_done) s.scale = 0.0;
+        return;
+    }
     if (s.rr <= tol2 * s.bb) s.outer_done = 1;
     s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
+}
+
+// after a reliable update: rho = <rhat, r>, the reference ||r||^2 for the next
+// update, and every unfinished lane active again
+__global__ void k_sc_ru_refresh(const double2* part, int nparts, RhsScal* sc) {
+    cd q[2];
+    fold<2>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    RhsScal& s = sc[blockIdx.x];
+    s.rho = q[0];
+    s.irr = q[1].re;
+    s.ibb = q[1].re;
+    s.best = q[1].re;
+    s.since = 0;
+    s.breakdown = 0;
+    s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
+    s.alpha = s.omega = s.beta = mk(0.0, 0.0);
 }
 
 // inner BiCGStab start: rho = <rhat, r> = ||r||^2 (rhat = r)
@@ -290,6 +376,8 @@ __global__ void k_sc_bicg_init(const double2* part, int nparts, RhsScal* sc) {
     s.rho = q[0];
     s.irr = q[0].re;
     s.ibb = q[0].re;
+    s.best = q[0].re;
+    s.since = 0;
     s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
     s.breakdown = 0;
     s.alpha = s.omega = s.beta = mk(0.0, 0.0);
@@ -336,15 +424,38 @@ __global__ void k_sc_bicg_omega_beta(const double2* part, int nparts, RhsScal* s
     s.rho = rho_new;
 }
 
-// partial ||r||^2 -> inner convergence relative to the inner start
-__global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, double tol2) {
+// partial ||r||^2 -> inner convergence relative to the inner start.  With
+// stall > 0, a lane whose ||r|| has not halved within stall iterations stops
+// and is marked as broken down (reliable updates then restart its Krylov
+// process; defect correction starts its next cycle).
+__global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, double tol2, int stall) {
     cd q[1];
     fold<1>(part, blockIdx.x, nparts, q);
     if (threadIdx.x) return;
     RhsScal& s = sc[blockIdx.x];
     if (!s.active) return;
     s.irr = q[0].re;
-    if (s.irr <= tol2 * s.ibb) s.active = 0;
+    if (s.irr <= tol2 * s.ibb) {
+        s.active = 0;
+        return;
+    }
+    if (!(s.irr <= 1e12 * s.best)) {
+        // blown up (||r|| a million times its best, or not a number): stop,
+        // and the correction is discarded rather than folded into the
+        // solution (transient BiCGStab spikes stay far below this)
+        s.active = 0;
+        s.breakdown = 2;
+        return;
+    }
+    if (stall > 0) {
+        if (s.irr < 0.25 * s.best) {
+            s.best = s.irr;
+            s.since = 0;
+        } else if (++s.since >= stall) {
+            s.active = 0;
+            s.breakdown = 1;
+        }
+    }
 }
 
 // CGNR: mode 0 init gam = ||z||^2 ; mode 1 alpha = gam / ||w||^2 ; mode 2 rr = ||r||^2 ;
@@ -505,9 +616,13 @@ static void op_apply(Work& w, const InnerOp& op, int prec, const void* in, void*
 // inner BiCGStab on op e = rin (normalised defect) in storage IO
 // hint: iterations the previous inner solve of this system took; that many
 // chunks (less one) run back to back before the host first reads the state.
+// refresh (reliable updates): called, with w.V at the full lattice, whenever
+// an unfinished lane's inner residual has fallen by inner_tol (or broken down);
+// it refreshes the inner state and returns false once every lane is finished.
 template <class IO>
 static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void* e, const uint8_t* mask,
-                    double inner_tol, int max_iter, int check_every, int hint = 0) {
+                    double inner_tol, int max_iter, int check_every, int hint = 0,
+                    const std::function<bool()>* refresh = nullptr, int stall = 0) {
     disco_ctx* ctx = w.ctx;
     const long Vfull = w.V;
     w.V = op.Vv;  // vector helpers below work on the operator's vectors
@@ -538,15 +653,15 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
                  disco::EPI_DOTAUX | disco::EPI_NORM | disco::EPI_DOTIN | disco::EPI_DOTAUXIN, tmp);
         k_sc_bicg_omega_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_xrp<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, v, r, g, w.sc, w.part);
-        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2);
+        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2, stall);
     };
     // A chunk of check_every iterations is captured once as a graph and replayed
     // between the host's convergence reads (eager when profiling or disabled).
     hipGraphExec_t exec = nullptr;
     if (ctx->opt_graphs && !ctx->prof_on && check_every > 1) {
         char key[512];
-        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g", prec, w.n, check_every,
-                 op.eo ? 1 : 0, (void*)mask, r, rh, p, v, s, t, e, tmp, (void*)w.sc, (void*)w.part, tol2);
+        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g/%d", prec, w.n, check_every,
+                 op.eo ? 1 : 0, (void*)mask, r, rh, p, v, s, t, e, tmp, (void*)w.sc, (void*)w.part, tol2, stall);
         auto itg = ctx->graphs.find(key);
         if (itg != ctx->graphs.end()) {
             exec = itg->second;
@@ -592,6 +707,22 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
             continue;
         }
         pull(w);
+        if (refresh) {
+            bool open = false, need = false;
+            for (auto& sc : w.h) {
+                if (sc.outer_done) continue;
+                open = true;
+                need |= sc.active == 0;
+            }
+            if (!open) break;
+            if (need) {
+                w.V = Vfull;
+                const bool more = (*refresh)();
+                w.V = op.Vv;
+                if (!more) break;
+            }
+            continue;
+        }
         bool any = false;
         for (auto& sc : w.h) any |= sc.active != 0;
         if (!any) break;
@@ -669,7 +800,7 @@ __global__ void k_eo_clover_inv(const void* __restrict__ in, void* __restrict__ 
 //   e_o = A_oo^-1 (r_o + kappa H_oe e_e).
 template <class IO>
 static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol,
-                       int max_iter, int check_every, int hint = 0) {
+                       int max_iter, int check_every, int hint = 0, int stall = 0) {
     disco_ctx* ctx = w.ctx;
     const long V = w.V;
     const int n = w.n;
@@ -693,7 +824,7 @@ static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_
     op.eo = true;
     op.Vv = V / 2;
     op.nsb = disco::stencil_nsb(ctx, n, true);
-    const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every, hint);
+    const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every, hint, nullptr, stall);
     disco::StencilCall cr{prec, 0, n, ee, eo, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
     disco::stencil_launch(ctx, cr);
     hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, ee, eo, e, V, n, Lx, Ly, Lz);
@@ -727,7 +858,10 @@ static void cgnr_correct(Work& w, const double2* b64, double2* x64, double2* r64
     const double rtol = std::max(1e-16, 0.5 * tol / worst);
     cgnr_run(w, r64, e, mask, rtol, max_iter, check, iters);
     std::vector<RhsScal> h = outer_state;
-    for (auto& s : h) s.scale = 1.0;  // x += e for the right-hand sides still running
+    for (auto& s : h) {
+        s.scale = 1.0;  // x += e for the right-hand sides still running
+        s.breakdown = 0;
+    }
     push(w, h);
     dc_update<IO64>(w, x64, e);
     push(w, outer_state);
@@ -781,12 +915,14 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
         copy_scale<IO64, IO>(w, r64, rin, 1);
         int ran;
         if (use_eo) {
-            ran = bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint);
+            ran = bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint,
+                                  kRuStall);
         } else {
             InnerOp op;
             op.Vv = w.V;
             op.nsb = w.nsb;
-            ran = bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint);
+            ran = bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint,
+                               nullptr, kRuStall);
         }
         iters += ran;
         hint = ran;
@@ -804,6 +940,127 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
         if (trace) fprintf(stderr, "[disco] fallback CGNR %d iterations\n", iters - before);
     }
     fill_stats(w, P, iters, outer, fb, st);
+}
+
+// BiCGStab in inner precision with reliable updates (BICGSTAB_RU).  One
+// Krylov process runs for the whole solve instead of one per defect-
+// correction cycle.  Whenever the recursive residual of an unfinished lane
+// has fallen by inner_tol since the last update, every lane's correction is
+// folded into the FP64 solution, the FP64 true residual is recomputed, and
+// the inner system's residual is replaced by the one it gives (its source in
+// even-odd form), with the search direction adjusted to match; the shadow
+// residual and the scalars carry on.  Lanes that break down, or whose true
+// residual does not follow the recursive one, restart their Krylov process.
+// The inner vectors keep the scale 1/||b|| of the start.
+template <class IO>
+static void ru_solve(Work& w, const disco_solver_params& P, int prec, const double2* b64, double2* x64,
+                     const uint8_t* mask, disco_solver_stats* st) {
+    disco_ctx* ctx = w.ctx;
+    const int n = w.n;
+    const long V = w.V;
+    const size_t nb64 = disco::native_bytes(ctx, DISCO_F64, n);
+    const size_t nbp = disco::native_bytes(ctx, prec, n);
+    double2* r64 = (double2*)ws_get(ctx, "dc_r64", nb64);
+    void* rin = ws_get(ctx, "dc_rin", nbp);
+    void* efull = ws_get(ctx, "dc_e", nbp);
+    const VecGeo g64 = vgeo(V, DISCO_F64, n);
+    const double tol2 = P.tol * P.tol;
+    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+    norm2<IO64>(w, b64, g64);
+    k_sc_outer<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    copy_scale<IO64, IO64>(w, b64, r64, 0);
+    const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+    const int check = P.check_every > 0 ? P.check_every : 2;
+    const double delta = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-3);
+    const bool eo = ctx->opt_eo && disco::eo_supported(ctx);
+    const long Vv = eo ? V / 2 : V;
+    const size_t hb = eo ? nbp / 2 : nbp;
+    const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2];
+    const double k = ctx->kappa;
+    void* re = eo ? ws_get(ctx, "eo_re", hb) : nullptr;
+    void* ro = eo ? ws_get(ctx, "eo_ro", hb) : nullptr;
+    void* uo = eo ? ws_get(ctx, "eo_uo", hb) : nullptr;
+    void* rhat = eo ? ws_get(ctx, "eo_rhat", hb) : rin;
+    void* ee = eo ? ws_get(ctx, "eo_ee", hb) : efull;
+    void* eodd = eo ? ws_get(ctx, "eo_eo", hb) : nullptr;
+    const void* Ai = prec == DISCO_F64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32;
+    // rin (full lattice) -> rhat: the inner system's source
+    auto prepare = [&]() {
+        if (!eo) return;
+        hipLaunchKernelGGL(k_eo_split<IO>, dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, rin, re, ro, V, n, Lx,
+                           Ly, Lz);
+        hipLaunchKernelGGL(k_eo_clover_inv<IO>, dim3(site_grid(V / 2, n)), dim3(256), 0, ctx->stream, ro, uo, Ai, V,
+                           n, 1, Lx, Ly, Lz);
+        disco::StencilCall cp{prec, 0, n, uo, rhat, re, nullptr, mask, nullptr, disco::EPI_NONE, 0, 0.0, 1.0, k};
+        disco::stencil_launch(ctx, cp);
+    };
+    // ee -> efull (odd sites from the source the correction belongs to)
+    auto reconstruct = [&]() {
+        if (!eo) return;
+        disco::StencilCall cr{prec, 0, n, ee, eodd, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
+        disco::stencil_launch(ctx, cr);
+        hipLaunchKernelGGL(k_eo_merge<IO>, dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, ee, eodd, efull, V, n,
+                           Lx, Ly, Lz);
+    };
+    // fold the correction into x64 and recompute the FP64 true residual
+    auto fold_in = [&]() {
+        reconstruct();
+        dc_update<IO>(w, x64, efull);
+        stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
+        k_sc_outer<<<n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 2, tol2);
+        pull(w);
+    };
+    InnerOp op;
+    op.eo = eo;
+    op.Vv = Vv;
+    op.nsb = disco::stencil_nsb(ctx, n, eo);
+    copy_scale<IO64, IO>(w, r64, rin, 1);
+    prepare();
+    int outer = 0, stall = 0;
+    double last_worst = 1e300;
+    const bool trace = getenv("DISCO_TRACE") != nullptr;
+    std::function<bool()> refresh = [&]() -> bool {
+        fold_in();
+        outer++;
+        bool open = false;
+        double worst = 0;
+        for (auto& s : w.h) {
+            open |= !s.outer_done;
+            if (s.bb > 0) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+        }
+        if (trace) fprintf(stderr, "[disco] reliable update %d: worst true rel residual %.3e\n", outer, worst);
+        if (!open) return false;
+        stall = worst > 0.5 * last_worst ? stall + 1 : 0;
+        last_worst = std::min(last_worst, worst);
+        if (stall >= 8) return false;  // no progress: leave it to the fallback
+        copy_scale<IO64, IO>(w, r64, rin, 1);
+        prepare();
+        const VecGeo gh = vgeo(Vv, prec, n);
+        void* r = ws_get(ctx, "bi_r", nbp);
+        void* rh = ws_get(ctx, "bi_rh", nbp);
+        void* p = ws_get(ctx, "bi_p", nbp);
+        hipLaunchKernelGGL(k_ru_refresh<IO>, dim3(gh.nb), dim3(gh.bd), 0, ctx->stream, r, rhat, p, rh, ee, gh, w.sc,
+                           w.part);
+        k_sc_ru_refresh<<<n, 256, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
+        HIPCHK(hipGetLastError());
+        return true;
+    };
+    const int iters = bicg_run<IO>(w, op, prec, rhat, ee, mask, delta, max_iter, check, 0, &refresh, kRuStall);
+    pull(w);
+    bool done = true;
+    for (auto& s : w.h) done &= s.outer_done != 0;
+    if (!done) {
+        fold_in();  // the correction since the last update (zero right after one)
+        done = true;
+        for (auto& s : w.h) done &= s.outer_done != 0;
+    }
+    int fb = 0;
+    int total = iters;
+    if (!done && P.fallback) {
+        fb = 1;
+        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, max_iter - iters), check, &total);
+    }
+    fill_stats(w, P, total, std::max(1, outer), fb, st);
 }
 
 // --------------------------------------------------------------- FGMRES
@@ -1093,6 +1350,13 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
             disco_throw(DISCO_EINVAL, "bad inner precision %d", P.inner_prec);
     } else if (P.method == DISCO_FGMRES_NN) {
         fgmres_solve(w, P, b64, x64, mask, st);
+    } else if (P.method == DISCO_BICGSTAB_RU) {
+        if (P.inner_prec == DISCO_F32)
+            ru_solve<IO32>(w, P, DISCO_F32, b64, x64, mask, st);
+        else if (P.inner_prec == DISCO_BF16)
+            ru_solve<IOBF>(w, P, DISCO_BF16, b64, x64, mask, st);
+        else
+            disco_throw(DISCO_EINVAL, "reliable updates need FP32 or BF16 inner precision, not %d", P.inner_prec);
     } else {
         disco_throw(DISCO_EINVAL, "unknown solver method %d", P.method);
     }
@@ -1100,7 +1364,8 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
 
 int default_rhs_block(const disco_solver_params& P, int nrhs, const disco_ctx* ctx) {
     int b = P.rhs_block;
-    if (b <= 0 && ctx && P.method == DISCO_BICGSTAB_DC && P.inner_prec >= 0 && P.inner_prec <= 2)
+    if (b <= 0 && ctx && (P.method == DISCO_BICGSTAB_DC || P.method == DISCO_BICGSTAB_RU) && P.inner_prec >= 0 &&
+        P.inner_prec <= 2)
         b = ctx->tuned_block[P.inner_prec];
     if (b <= 0) b = 16;
     return std::max(1, std::min({b, nrhs, 64, max_rhs_block(ctx)}));

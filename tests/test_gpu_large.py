@@ -1,6 +1,7 @@
 """Parity at the larger workload shapes: 24^3x48 (the batching configuration,
 with regular and edge-remainder domains) and 32^3x64 (the production-sized
-lattice, with 8^3x16 and 16^3x32 domains).  The oracle cannot solve at these
+lattice, with 8^3x16 and 16^3x32 domains), each with defect correction and
+with reliable updates.  The oracle cannot solve at these
 sizes in test time, so each solution is judged by the oracle's FP64 operator:
 the true relative residual of the full or domain-restricted system, computed
 on the host, must meet the tolerance, and must agree with the residual the
@@ -29,10 +30,11 @@ def disco():
     return d
 
 
-def _check(disco, ctx, U, A, pre, cut, inner, nrhs, seed, tol):
+def _check(disco, ctx, U, A, pre, cut, inner, nrhs, seed, tol, method=None):
     dom = ctx.domains(cut) if cut is not None else None
     b = synth.random_spinor(ctx.V, nrhs, seed)
-    P = ctx.params(method=disco.BICGSTAB_DC, tol=tol, inner_prec=inner, rhs_block=nrhs)
+    method = disco.BICGSTAB_DC if method is None else method
+    P = ctx.params(method=method, tol=tol, inner_prec=inner, rhs_block=nrhs)
     x, st = ctx.solve_multi_rhs(ctx.dev(b), P, dom)
     x = x.cpu().numpy()
     for k in range(nrhs):
@@ -67,6 +69,8 @@ def test_batching_shape_24x24x24x48(disco, batch_cfg, domains):
         cut = synth.offset_tiling_cuts(pre.dims, pre.block)
     _say("24^3x48 FP32-inner solve, domains", domains)
     _check(disco, ctx, U, A, pre, cut, disco.F32, 8, 61, 1e-10)
+    _say("24^3x48 BF16-inner solve with reliable updates, domains", domains)
+    _check(disco, ctx, U, A, pre, cut, disco.BF16, 8, 64, 1e-10, disco.BICGSTAB_RU)
 
 
 @pytest.fixture(scope="module")
@@ -87,3 +91,5 @@ def test_production_shape_32x32x32x64(disco, prod_cfg, block):
     cut = None if block is None else synth.tiling_cuts(pre.dims, block)
     _say("32^3x64 BF16-storage solve, block", block)
     _check(disco, ctx, U, A, pre, cut, disco.BF16, 4, 62, 1e-10)
+    _say("32^3x64 BF16-storage solve with reliable updates, block", block)
+    _check(disco, ctx, U, A, pre, cut, disco.BF16, 4, 65, 1e-10, disco.BICGSTAB_RU)

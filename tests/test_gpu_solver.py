@@ -1,5 +1,6 @@
-"""GPU parity of the solvers: FP64 CGNR and BiCGStab with FP32/BF16 inner
-solves inside FP64 defect correction, full and domain-restricted operators.
+"""GPU parity of the solvers: FP64 CGNR, BiCGStab with FP32/BF16 inner
+solves inside FP64 defect correction, and BiCGStab with reliable updates,
+full and domain-restricted operators.
 Judged by the oracle: its own solution on small lattices, and the true
 residual computed with the oracle's operator at the full workload size."""
 import sys
@@ -43,7 +44,7 @@ def _true_rel_res(U, A, dims, kappa, b, x, cut=None):
 
 
 @pytest.mark.parametrize("method,inner", [("CGNR_F64", "F64"), ("BICGSTAB_DC", "F32"), ("BICGSTAB_DC", "BF16"),
-                                          ("BICGSTAB_DC", "F64")])
+                                          ("BICGSTAB_DC", "F64"), ("BICGSTAB_RU", "F32"), ("BICGSTAB_RU", "BF16")])
 @pytest.mark.parametrize("blocked", [False, True])
 def test_solver_matches_oracle_small(disco, plain, method, inner, blocked):
     pre, ctx, U, A = plain
@@ -107,7 +108,8 @@ def test_batched_equals_unbatched(disco, plain):
 
 def test_full_size_mixed_precision_solve(disco):
     """16^3 x 32 mixed-precision workload: FP32 and BF16 inner BiCGStab with
-    FP64 defect correction to 1e-10, full and block operator; the true
+    FP64 defect correction and with reliable updates to 1e-10, full and block
+    operator; the true
     residual is recomputed with the oracle's FP64 operator."""
     pre = synth.PRESETS["prec_16x16x16x32"]
     dims = pre.dims
@@ -121,10 +123,11 @@ def test_full_size_mixed_precision_solve(disco):
     cut = synth.tiling_cuts(dims, pre.block)
     dom = ctx.domains(cut)
     b = synth.random_spinor(V, 16, 55)
-    for inner in (disco.F32, disco.BF16):
+    for method, inner in ((disco.BICGSTAB_DC, disco.F32), (disco.BICGSTAB_DC, disco.BF16),
+                          (disco.BICGSTAB_RU, disco.F32), (disco.BICGSTAB_RU, disco.BF16)):
         for d, c in ((None, None), (dom, cut)):
-            _say("  inner", inner, "block" if d else "full")
-            P = ctx.params(tol=1e-10, inner_prec=inner, rhs_block=16)
+            _say("  method", method, "inner", inner, "block" if d else "full")
+            P = ctx.params(method=method, tol=1e-10, inner_prec=inner, rhs_block=16)
             x, st = ctx.solve_multi_rhs(ctx.dev(b), P, d)
             x = x.cpu().numpy()
             rr = _true_rel_res(U, A, dims, pre.kappa, b[:3], x[:3], c)
@@ -145,15 +148,16 @@ def test_graph_replays_equal_eager(disco):
     V = int(np.prod(dims))
     b = ctx.dev(synth.random_spinor(V, 24, 22))
     out = {}
+    cases = [(m, i) for m in (disco.BICGSTAB_DC, disco.BICGSTAB_RU) for i in (disco.F32, disco.BF16)]
     for g in (0, 1):
         ctx.set_option(disco.OPT_GRAPHS, g)
-        for inner in (disco.F32, disco.BF16):
-            P = ctx.params(tol=1e-11, inner_prec=inner, rhs_block=8, check_every=5)
+        for m, inner in cases:
+            P = ctx.params(method=m, tol=1e-11, inner_prec=inner, rhs_block=8, check_every=5)
             x, st = ctx.solve_multi_rhs(b, P)
-            out[(g, inner)] = (x.cpu().numpy(), [s.iters for s in st])
-    for inner in (disco.F32, disco.BF16):
-        assert out[(0, inner)][1] == out[(1, inner)][1]
-        assert np.array_equal(out[(0, inner)][0], out[(1, inner)][0])
+            out[(g, m, inner)] = (x.cpu().numpy(), [s.iters for s in st], [s.outer_iters for s in st])
+    for m, inner in cases:
+        assert out[(0, m, inner)][1:] == out[(1, m, inner)][1:]
+        assert np.array_equal(out[(0, m, inner)][0], out[(1, m, inner)][0])
     ctx.set_option(disco.OPT_GRAPHS, 1)
 
 
@@ -222,3 +226,58 @@ def test_even_odd_inner_solves(disco, inner, blocked):
         iters[eo] = st[0].iters
     ctx.set_option(disco.OPT_EO, 1)
     assert iters[1] <= iters[0]
+
+
+@pytest.mark.parametrize("inner", ["F32", "BF16"])
+@pytest.mark.parametrize("eo", [1, 0])
+@pytest.mark.parametrize("blocked", [False, True])
+def test_reliable_updates(disco, inner, eo, blocked):
+    """BiCGStab with reliable updates, on the even-odd Schur complement and on
+    the full operator, full and domain-restricted: every right-hand side meets
+    the tolerance by the oracle's FP64 true residual, without the fallback,
+    with the residual the library reports; a zero right-hand side stays zero."""
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.124, 1.2
+    U = synth.gauge_field(dims, 0.3, 61)
+    A = oracle.clover(U, dims, kappa, csw)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, csw)
+    ctx.set_option(disco.OPT_EO, eo)
+    cut = synth.tiling_cuts(dims, (4, 4, 4, 4)) if blocked else None
+    dom = ctx.domains(cut) if blocked else None
+    b = synth.random_spinor(ctx.V, 6, 62)
+    b[3] = 0
+    tol = 1e-12 if inner == "F32" else 1e-10
+    P = ctx.params(method=disco.BICGSTAB_RU, tol=tol, inner_prec=getattr(disco, inner), rhs_block=6)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, dom)
+    ctx.set_option(disco.OPT_EO, 1)
+    x = x.cpu().numpy()
+    assert np.abs(x[3]).max() == 0
+    live = [0, 1, 2, 4, 5]
+    rr = _true_rel_res(U, A, dims, kappa, b[live], x[live], cut)
+    _say("  reliable updates %s eo %d blocked %s: %d iterations, %d updates, oracle residual %.2e" %
+         (inner, eo, blocked, st[0].iters, st[0].outer_iters, rr.max()))
+    assert all(s.fallback_used == 0 for s in st)
+    assert rr.max() <= tol * 1.05
+    for k, i in enumerate(live):
+        assert abs(rr[k] - st[i].true_rel_residual) <= max(1e-2 * rr[k], 2e-15)
+
+
+def test_reliable_updates_fallback_and_errors(disco, plain):
+    """An iteration cap below what the inner process needs hands over to the
+    FP64 CGNR fallback, which reports its result truthfully; FP64 storage is
+    not a reliable-update precision."""
+    pre, ctx, U, A = plain
+    V = int(np.prod(pre.dims))
+    b = synth.random_spinor(V, 3, 63)
+    P = ctx.params(method=disco.BICGSTAB_RU, tol=1e-12, inner_prec=disco.BF16, max_iter=6, rhs_block=3)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, allow_noconv=True)
+    assert all(s.fallback_used == 1 for s in st)
+    rr = _true_rel_res(U, A, pre.dims, pre.kappa, b, x.cpu().numpy())
+    for k in range(3):
+        assert abs(rr[k] - st[k].true_rel_residual) <= max(1e-2 * rr[k], 2e-15)
+        assert st[k].converged == (rr[k] <= 1e-12 * 1.01)
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.solve_multi_rhs(ctx.dev(b), ctx.params(method=disco.BICGSTAB_RU, tol=1e-10, inner_prec=disco.F64))
+    assert e.value.code == disco.EINVAL
