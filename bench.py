@@ -282,12 +282,14 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # The production steps above run their inner iterations as HIP graphs; the
-    # per-launch stencil times come from one more step with every stencil
-    # launch bracketed by HIP events on the context stream (eager launches).
+    # per-launch stencil times come from one more pass of a step's full-operator
+    # solves (the dominant launches: the unmasked stencil; the D_Lambda solves use
+    # the masked instance) with every stencil launch bracketed by HIP events on
+    # the context stream (eager launches), and its projections.
     ctx.profile_reset()
     ctx.profile_stride(1)
     ctx.profile_enable(True)
-    step(args.warmup + args.steps)
+    ctx.perambulators_tt(Vev, groups[(args.warmup + args.steps) % len(groups)], P, tau_f)
     ctx.profile_enable(False)
     # dominant kernel: the inner-precision stencil family with the most launches
     # (the even-odd half-lattice stencil when every extent is even)
@@ -312,15 +314,16 @@ def main():
     gbps = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     blk = args.rhs_block or tuned
     tflops = FLOP_PER_SITE_RHS * sites * blk / (avg_ms / 1e3) / 1e12 if avg_ms > 0 else 0.0
-    # The stencil saturates neither unit (memory latency): its measured HBM traffic
-    # is the nearer bound, so the roofline is HBM, with the vector-ALU rate beside it.
+    # The stencil saturates neither unit: its measured HBM traffic is the nearer
+    # bound, so the roofline is HBM, with the vector-ALU rate beside it.
     traffic = load_traffic("%s/n%d" % (kernel_tag, blk))
     roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "traffic_gbps": round(traffic / (avg_ms / 1e3) / 1e9, 1) if traffic else None,
             "alu_tflops": round(tflops, 2), "alu_peak_tflops": round(VALU_FP32_PEAK_TFLOPS, 1),
             "alu_frac": round(tflops / VALU_FP32_PEAK_TFLOPS, 4),
-            "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, %d RHS per launch, %d sites)" % (blk, sites),
+            "kernel": kernel_tag + " (inner-precision Wilson-clover stencil, full operator, %d RHS per launch, %d sites)"
+            % (blk, sites),
             "avg_launch_ms": round(avg_ms, 5), "launches_timed": nl,
             "alg_bytes_per_launch": round(by / max(nl, 1)),
             "flop_per_launch": FLOP_PER_SITE_RHS * sites * blk}

@@ -616,13 +616,14 @@ static void op_apply(Work& w, const InnerOp& op, int prec, const void* in, void*
 // inner BiCGStab on op e = rin (normalised defect) in storage IO
 // hint: iterations the previous inner solve of this system took; that many
 // chunks (less one) run back to back before the host first reads the state.
-// refresh (reliable updates): called, with w.V at the full lattice, whenever
-// an unfinished lane's inner residual has fallen by inner_tol (or broken down);
-// it refreshes the inner state and returns false once every lane is finished.
+// refresh (reliable updates): called, with w.V at the full lattice and the
+// iterations so far, whenever an unfinished lane's inner residual has fallen
+// by inner_tol (or broken down); it refreshes the inner state and returns
+// false once every lane is finished (or it gives up).
 template <class IO>
 static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void* e, const uint8_t* mask,
                     double inner_tol, int max_iter, int check_every, int hint = 0,
-                    const std::function<bool()>* refresh = nullptr, int stall = 0) {
+                    const std::function<bool(int)>* refresh = nullptr, int stall = 0) {
     disco_ctx* ctx = w.ctx;
     const long Vfull = w.V;
     w.V = op.Vv;  // vector helpers below work on the operator's vectors
@@ -694,6 +695,7 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
     }
     int it = 0;
     int blind = std::max(0, hint - check_every) / check_every;
+    int last_update = 0;
     while (it < max_iter) {
         if (exec && max_iter - it >= check_every) {
             HIPCHK(hipGraphLaunch(exec, ctx->stream));
@@ -717,9 +719,13 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
             if (!open) break;
             if (need) {
                 w.V = Vfull;
-                const bool more = (*refresh)();
+                const bool more = (*refresh)(it);
                 w.V = op.Vv;
                 if (!more) break;
+                // the next update is likely about as far away as this one was:
+                // run half that many iterations without host reads
+                blind = std::max(0, (it - last_update) / 2 - check_every) / check_every;
+                last_update = it;
             }
             continue;
         }
@@ -1016,10 +1022,10 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, const doub
     op.nsb = disco::stencil_nsb(ctx, n, eo);
     copy_scale<IO64, IO>(w, r64, rin, 1);
     prepare();
-    int outer = 0, stall = 0;
+    int outer = 0, stall = 0, it_best = 0;
     double last_worst = 1e300;
     const bool trace = getenv("DISCO_TRACE") != nullptr;
-    std::function<bool()> refresh = [&]() -> bool {
+    std::function<bool(int)> refresh = [&](int it) -> bool {
         fold_in();
         outer++;
         bool open = false;
@@ -1030,9 +1036,16 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, const doub
         }
         if (trace) fprintf(stderr, "[disco] reliable update %d: worst true rel residual %.3e\n", outer, worst);
         if (!open) return false;
-        stall = worst > 0.5 * last_worst ? stall + 1 : 0;
+        if (worst > 0.5 * last_worst) {
+            stall++;
+        } else {
+            stall = 0;
+            it_best = it;
+        }
         last_worst = std::min(last_worst, worst);
-        if (stall >= 8) return false;  // no progress: leave it to the fallback
+        // no halving of the worst true residual over 8 updates and 800
+        // iterations (lanes restart on their own after 100): leave it to the fallback
+        if (stall >= 8 && it - it_best >= 800) return false;
         copy_scale<IO64, IO>(w, r64, rin, 1);
         prepare();
         const VecGeo gh = vgeo(Vv, prec, n);

@@ -55,6 +55,8 @@ struct StencilArgs {
     int n;     // right-hand sides in the block
     int dagger;
     int stage; // LDS staging requested (applies to FP32 links with at most kStageSites sites per block)
+    unsigned allhops;  // 0xff: the hop word of the unmasked instance (an argument, not a constant, so
+                       // that the hops stay separate blocks and the compiler does not hoist all loads)
 };
 
 // ---- spin projection (1 - gamma_mu) [FWD] or (1 + gamma_mu) [BWD], chiral basis
@@ -240,7 +242,9 @@ constexpr int kStageSites = 32;
 constexpr int kStageLinkBytes = 8 * 9 * 8;   // 8 links x 9 complex float
 constexpr int kStageCloverBytes = 18 * 16;   // 2 blocks x 9 float4
 
-template <class IO, int EPI, bool BUF, bool STAGE, bool EO>
+// MASK = false: the full operator (every hop present, no mask load; the hop
+// tests are uniform).  MASK = true: hops removed where the domain mask says so.
+template <class IO, int EPI, bool BUF, bool STAGE, bool EO, bool MASK>
 __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
     typedef typename IO::T T;
     constexpr int NQ = EpiCount<EPI>::nq;
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         const int2 tr = a.trav[g];
         const int s = tr.x;
         const int x[4] = {tr.y & 0xff, (tr.y >> 8) & 0xff, (tr.y >> 16) & 0xff, (tr.y >> 24) & 0xff};
-        const uint32_t m = a.mask ? (uint32_t)a.mask[s] : 0xffu;
+        const uint32_t m = (MASK && a.mask) ? (uint32_t)a.mask[s] : a.allhops;
         cx<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = mk((T)0, (T)0);
@@ -452,21 +456,28 @@ __global__ void k_from_native(const void* __restrict__ in, double2* __restrict__
     for (int k = 0; k < 12; k++) q[k] = make_double2((double)p[k].re, (double)p[k].im);
 }
 
+// (the large-volume path without buffer descriptors keeps one generic
+// instance that reads the mask when there is one)
 template <class IO, int EPI, bool EO>
 void launch_one(disco_ctx* ctx, const StencilArgs& a) {
     const dim3 grid(xcd_grid(a.nsb)), block(kStencilBlock);
     const bool stage = sizeof(typename IO::T) == 4 && a.spb <= kStageSites && a.stage;
+    const bool masked = a.mask != nullptr;
     if (stage) {
         const size_t shm = (size_t)a.spb * (kStageLinkBytes + kStageCloverBytes);
-        if (a.in.buf)
-            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true, EO>), grid, block, shm, ctx->stream, a);
+        if (a.in.buf && masked)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true, EO, true>), grid, block, shm, ctx->stream, a);
+        else if (a.in.buf)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, true, EO, false>), grid, block, shm, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_dslash<IO, EPI, false, true, EO>), grid, block, shm, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, true, EO, true>), grid, block, shm, ctx->stream, a);
     } else {
-        if (a.in.buf)
-            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false, EO>), grid, block, 0, ctx->stream, a);
+        if (a.in.buf && masked)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false, EO, true>), grid, block, 0, ctx->stream, a);
+        else if (a.in.buf)
+            hipLaunchKernelGGL((k_dslash<IO, EPI, true, false, EO, false>), grid, block, 0, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_dslash<IO, EPI, false, false, EO>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_dslash<IO, EPI, false, false, EO, true>), grid, block, 0, ctx->stream, a);
     }
 }
 
@@ -597,6 +608,7 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     a.aux = RoView{c.aux, (unsigned)blk, buf};
     a.aux2 = RoView{c.aux2, (unsigned)blk, buf};
     a.mask = c.mask;
+    a.allhops = 0xffu;
     a.trav = eo ? ctx->d_trav_eo[c.eo_target] : ctx->d_trav;
     a.part = c.part;
     a.V = ctx->V;

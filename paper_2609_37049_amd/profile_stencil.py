@@ -6,8 +6,8 @@
 Launches the Wilson-clover stencil on native blocks of random spinors in the
 launch configuration the solver uses (nrhs right-hand sides per launch, LDS
 staging as the library chooses).  Then, with --solver-iters K > 0, runs K
-inner iterations of the mixed-precision BiCGStab on nrhs random right-hand
-sides with HIP graphs off, so that every stencil launch the solver makes
+inner iterations of the mixed-precision BiCGStab (reliable updates) on nrhs
+random right-hand sides with HIP graphs off, so that every stencil launch the solver makes
 (with its dot-product epilogues) is an ordinary dispatch a counter run can
 see.  Last comes a plain 256 MiB device-to-device copy whose byte counts
 calibrate the FETCH_SIZE / WRITE_SIZE counters.  Prints the algorithmic
@@ -57,7 +57,7 @@ def main():
         g = torch.Generator().manual_seed(5)
         b = torch.complex(torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64),
                           torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64)).cuda()
-        P = ctx.params(method=d.BICGSTAB_DC, tol=1e-10, max_iter=args.solver_iters, inner_prec=prec,
+        P = ctx.params(method=d.BICGSTAB_RU, tol=1e-10, max_iter=args.solver_iters, inner_prec=prec,
                        rhs_block=n, fallback=0, check_every=args.solver_iters)
         ctx.solve_multi_rhs(b, P, allow_noconv=True)
         torch.cuda.synchronize()
