@@ -898,7 +898,7 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
     const bool trace = getenv("DISCO_TRACE") != nullptr;
     const bool use_eo = ctx->opt_eo && disco::eo_supported(ctx);
     double last_worst = 1e300;
-    int stall = 0;
+    int stall = 0, it_best = 0;
     int hint = 0;
     while (true) {
         pull(w);
@@ -914,9 +914,16 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
             fprintf(stderr, "[disco] outer %d: worst true rel residual %.3e, %d/%d done, %d inner iterations\n",
                     outer, worst, nd, w.n, iters);
         if (done || iters >= max_iter) break;
-        stall = worst > 0.5 * last_worst ? stall + 1 : 0;
-        last_worst = worst;
-        if (stall >= 3) break;  // no progress: leave it to the fallback
+        // no halving of the worst true residual over 5 cycles and 800 inner
+        // iterations: leave it to the fallback
+        if (worst > 0.5 * last_worst) {
+            stall++;
+        } else {
+            stall = 0;
+            it_best = iters;
+        }
+        last_worst = std::min(last_worst, worst);
+        if (stall >= 5 && iters - it_best >= 800) break;
         outer++;
         copy_scale<IO64, IO>(w, r64, rin, 1);
         int ran;

@@ -376,47 +376,40 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
         int q = 0;
         cx<T> w[12];
         if (EPI & (disco::EPI_DOTAUX | disco::EPI_DOTAUXIN)) IO::template loadv<BUF>(a.aux2, Vv, n, r, sv, w);
+        // each lane's twelve-term sums in the arithmetic precision (FMA
+        // chains); the sums over lanes and blocks are FP64
         if (EPI & disco::EPI_DOTAUX) {
-            double re = 0, im = 0;
+            cx<T> acc = mk((T)0, (T)0);
 #pragma unroll
-            for (int k = 0; k < 12; k++) {
-                cx<T> d = cjmul(w[k], o[k]);
-                re += (double)d.re;
-                im += (double)d.im;
-            }
-            red[2 * q] = re;
-            red[2 * q + 1] = im;
+            for (int k = 0; k < 12; k++) cjmac(acc, w[k], o[k]);
+            red[2 * q] = (double)acc.re;
+            red[2 * q + 1] = (double)acc.im;
             q++;
         }
         if (EPI & disco::EPI_NORM) {
-            double nn = 0;
+            T nn = 0;
 #pragma unroll
-            for (int k = 0; k < 12; k++) nn += (double)nrm(o[k]);
-            red[2 * q] = nn;
+            for (int k = 0; k < 12; k++) {
+                nn = fma(o[k].re, o[k].re, nn);
+                nn = fma(o[k].im, o[k].im, nn);
+            }
+            red[2 * q] = (double)nn;
             q++;
         }
         if (EPI & disco::EPI_DOTIN) {
-            double re = 0, im = 0;
+            cx<T> acc = mk((T)0, (T)0);
 #pragma unroll
-            for (int k = 0; k < 12; k++) {
-                cx<T> d = cjmul(o[k], pin[k]);
-                re += (double)d.re;
-                im += (double)d.im;
-            }
-            red[2 * q] = re;
-            red[2 * q + 1] = im;
+            for (int k = 0; k < 12; k++) cjmac(acc, o[k], pin[k]);
+            red[2 * q] = (double)acc.re;
+            red[2 * q + 1] = (double)acc.im;
             q++;
         }
         if (EPI & disco::EPI_DOTAUXIN) {
-            double re = 0, im = 0;
+            cx<T> acc = mk((T)0, (T)0);
 #pragma unroll
-            for (int k = 0; k < 12; k++) {
-                cx<T> d = cjmul(w[k], pin[k]);
-                re += (double)d.re;
-                im += (double)d.im;
-            }
-            red[2 * q] = re;
-            red[2 * q + 1] = im;
+            for (int k = 0; k < 12; k++) cjmac(acc, w[k], pin[k]);
+            red[2 * q] = (double)acc.re;
+            red[2 * q + 1] = (double)acc.im;
             q++;
         }
     }
