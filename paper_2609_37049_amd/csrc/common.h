@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/disco.h"
@@ -265,7 +266,18 @@ int stencil_nsb(disco_ctx* ctx, int n, bool eo = false);
 // right-hand sides a stencil launch can address (32-bit offsets within a spinor plane)
 int plane_rhs_limit(const disco_ctx* ctx);
 // largest block of a batched solve: 64 and the plane limit
-int max_rhs_block(const disco_ctx* ctx);   // partial-sum slots per (rhs, quantity)
+int max_rhs_block(const disco_ctx* ctx);
+// A queue of right-hand sides that feeds the lanes of a native FP64 block of
+// `width` lanes: load writes right-hand side j into lane `lane` of b64; store
+// takes the solutions of finished lanes (with their right-hand sides' indices)
+// from x64 before the lanes are reused.
+struct LaneFeeder {
+    int total = 0;
+    std::function<void(int lane, int j, int width)> load;
+    std::function<void(const std::vector<int>& lanes, const std::vector<int>& js, int width)> store;
+};
+long long solve_fed(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, LaneFeeder& f,
+                    double2* b64, double2* x64, disco_solver_stats* st);   // partial-sum slots per (rhs, quantity)
 bool eo_supported(const disco_ctx* ctx);
 int stencil_spb(int n);                    // sites per stencil block
 void build_traversal(disco_ctx* ctx);

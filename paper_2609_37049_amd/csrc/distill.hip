@@ -369,15 +369,13 @@ struct SrcSpec {
     int i, alpha;
 };
 
-// eta_r(x) = sum_{t in tmask_r} delta_{x4,t} v_i(t; xs) (x) e_alpha, native FP64 [12][V][n]
-__global__ void k_sources(const double2* __restrict__ Vi /* [t][xs*3+c][nv] */, const SrcSpec* __restrict__ spec,
-                          double2* __restrict__ out, long V, long Vs, int nv, int n) {
-    const long tot = V * n;
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
-        const long s = q / n;
-        const int r = (int)(q - s * n);
+// eta(x) = sum_{t in tmask} delta_{x4,t} v_i(t; xs) (x) e_alpha for a source spec (i, alpha, tmask):
+// eta_r for one lane r of a width-n native block (the lane's spec in spec[r])
+__global__ void k_source_lane(const double2* __restrict__ Vi, const SrcSpec* __restrict__ spec,
+                              double2* __restrict__ out, long V, long Vs, int nv, int n, int r) {
+    const SrcSpec sp = spec[r];
+    for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
         const long t = s / Vs, xs = s - t * Vs;
-        const SrcSpec sp = spec[r];
         const bool on = (sp.tmask >> t) & 1ULL;
         for (int k = 0; k < 12; k++) {
             const int a = k / 3, c = k % 3;
@@ -385,6 +383,17 @@ __global__ void k_sources(const double2* __restrict__ Vi /* [t][xs*3+c][nv] */, 
             if (on && a == sp.alpha) v = Vi[((t * Vs + xs) * 3 + c) * nv + sp.i];
             out[((long)k * V + s) * n + r] = v;
         }
+    }
+}
+
+// lanes[q] of a width-n native FP64 block -> lane q of a width-m block
+__global__ void k_gather_lanes(const double2* __restrict__ X, double2* __restrict__ Y, long V, int n,
+                               const int* __restrict__ lanes, int m) {
+    const long tot = 12 * V * m;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long ks = i / m;
+        const int q = (int)(i - ks * m);
+        Y[i] = X[ks * n + lanes[q]];
     }
 }
 
@@ -974,43 +983,66 @@ int disco_perambulators_tt(disco_ctx* ctx, const disco_domains* dom, const void*
         }
         const int nrhs_set = 4 * nv;
         const int blk = disco::default_rhs_block(*P, nrhs_set, ctx);
+        // lane specs, and the specs and lanes of a hand-over (device; host staging beside)
         SrcSpec* specd = (SrcSpec*)ws_get(ctx, "ld_spec", sizeof(SrcSpec) * blk);
+        SrcSpec* specg = (SrcSpec*)ws_get(ctx, "ld_specg", sizeof(SrcSpec) * blk);
+        int* laneg = (int*)ws_get(ctx, "ld_lanes", sizeof(int) * blk);
         double2* b64 = (double2*)ws_get(ctx, "ld_b64", disco::native_bytes(ctx, DISCO_F64, blk));
         double2* x64 = (double2*)ws_get(ctx, "ld_x64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* xg = (double2*)ws_get(ctx, "ld_xg", disco::native_bytes(ctx, DISCO_F64, blk));
         double2* G = (double2*)ws_get(ctx, "ld_G", sizeof(double2) * K * 4 * blk);
         double2* C = (double2*)ws_get(ctx, "ld_C", sizeof(double2) * nv * 4 * blk);
-        std::vector<disco_solver_stats> st(blk);
-        long long solves = 0, iters = 0;
-        double worst = 0;
-        int fb = 0, outer = 0;
-        for (unsigned long long msk0 : sets) {
-            const unsigned long long msk = msk0 & tmask;
-            if (!msk) continue;
-            for (int r0 = 0; r0 < nrhs_set; r0 += blk) {
-                const int n = std::min(blk, nrhs_set - r0);
-                std::vector<SrcSpec> spec(n);
-                for (int r = 0; r < n; r++) spec[r] = SrcSpec{msk, (r0 + r) / 4, (r0 + r) % 4};
-                HIPCHK(hipMemcpyAsync(specd, spec.data(), sizeof(SrcSpec) * n, hipMemcpyHostToDevice, ctx->stream));
-                k_sources<<<grid_for(V * n), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, n);
-                HIPCHK(hipGetLastError());
-                disco::solve_native(ctx, dom, *P, n, b64, x64, st.data());
-                for (int r = 0; r < n; r++) {
-                    all_ok &= st[r].converged != 0;
-                    worst = std::max(worst, st[r].true_rel_residual);
+        std::vector<SrcSpec> hspec(blk), hspecg(blk);
+        std::vector<int> hlanes(blk);
+        // one queue over every source of every set (set k, source j: i = j / 4,
+        // alpha = j % 4), so that lanes never wait for a set to drain; each
+        // solution is projected as soon as it is final
+        std::vector<unsigned long long> qmask;
+        for (unsigned long long msk0 : sets)
+            if (msk0 & tmask) qmask.push_back(msk0 & tmask);
+        const int nq = (int)qmask.size() * nrhs_set;
+        auto spec_of = [&](int j) { return SrcSpec{qmask[j / nrhs_set], (j % nrhs_set) / 4, j % 4}; };
+        disco::LaneFeeder f;
+        f.total = nq;
+        f.load = [&](int lane, int j, int width) {
+            hspec[lane] = spec_of(j);
+            HIPCHK(hipMemcpyAsync(specd + lane, &hspec[lane], sizeof(SrcSpec), hipMemcpyHostToDevice, ctx->stream));
+            k_source_lane<<<grid_for(V), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, width, lane);
+        };
+        f.store = [&](const std::vector<int>& lanes, const std::vector<int>& js, int width) {
+            // the finished lanes, set by set
+            for (size_t k = 0; k < qmask.size(); k++) {
+                int m = 0;
+                for (size_t q = 0; q < lanes.size(); q++) {
+                    if (js[q] / nrhs_set != (int)k) continue;
+                    hspecg[m] = spec_of(js[q]);
+                    hlanes[m++] = lanes[q];
                 }
-                iters += st[0].iters;
-                outer += st[0].outer_iters;
-                fb |= st[0].fallback_used;
-                solves += n;
+                if (!m) continue;
+                const unsigned long long msk = qmask[k];
+                HIPCHK(hipMemcpyAsync(specg, hspecg.data(), sizeof(SrcSpec) * m, hipMemcpyHostToDevice, ctx->stream));
+                HIPCHK(hipMemcpyAsync(laneg, hlanes.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+                k_gather_lanes<<<grid_for(12 * V * m), 256, 0, ctx->stream>>>(x64, xg, V, width, laneg, m);
                 for (int t = 0; t < T; t++) {
                     if (!((msk >> t) & 1ULL)) continue;
-                    k_slab<<<grid_for(Vs * 12 * n), 256, 0, ctx->stream>>>(x64, G, V, Vs, n, t);
-                    zgemm_hn(ctx, Vi + (long)t * K * nv, nv, 0, G, 4L * n, 0, C, nv, 4 * n, (int)K, 1);
-                    k_tau_scatter<<<grid_for((long)nv * 4 * n), 256, 0, ctx->stream>>>(C, specd, tau, nv, n, t);
+                    k_slab<<<grid_for(Vs * 12 * m), 256, 0, ctx->stream>>>(xg, G, V, Vs, m, t);
+                    zgemm_hn(ctx, Vi + (long)t * K * nv, nv, 0, G, 4L * m, 0, C, nv, 4 * m, (int)K, 1);
+                    k_tau_scatter<<<grid_for((long)nv * 4 * m), 256, 0, ctx->stream>>>(C, specg, tau, nv, m, t);
                 }
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipStreamSynchronize(ctx->stream));  // spec buffer is reused by the next block
+                HIPCHK(hipStreamSynchronize(ctx->stream));  // the host staging is reused by the next set
             }
+        };
+        std::vector<disco_solver_stats> st(nq);
+        long long iters = disco::solve_fed(ctx, dom, *P, blk, f, b64, x64, st.data());
+        long long solves = nq;
+        double worst = 0;
+        int fb = 0, outer = 0;
+        for (int j = 0; j < nq; j++) {
+            all_ok &= st[j].converged != 0;
+            worst = std::max(worst, st[j].true_rel_residual);
+            fb |= st[j].fallback_used;
+            outer = std::max(outer, st[j].outer_iters);
         }
         if (agg) {
             agg->iters = (int)std::min<long long>(iters, 2147483647LL);
@@ -1179,44 +1211,61 @@ int disco_perambulators_all(disco_ctx* ctx, const void* Vin, int nv, unsigned lo
         const int blk = disco::default_rhs_block(*P, nrhs_set, ctx);
         const int kchunk = std::min(T, 8);  // sinks per batched contraction
         SrcSpec* specd = (SrcSpec*)ws_get(ctx, "ld_spec", sizeof(SrcSpec) * blk);
+        SrcSpec* specg = (SrcSpec*)ws_get(ctx, "ld_specg", sizeof(SrcSpec) * blk);
+        int* laneg = (int*)ws_get(ctx, "ld_lanes", sizeof(int) * blk);
         double2* b64 = (double2*)ws_get(ctx, "ld_b64", disco::native_bytes(ctx, DISCO_F64, blk));
         double2* x64 = (double2*)ws_get(ctx, "ld_x64", disco::native_bytes(ctx, DISCO_F64, blk));
+        double2* xg = (double2*)ws_get(ctx, "ld_xg", disco::native_bytes(ctx, DISCO_F64, blk));
         double2* G = (double2*)ws_get(ctx, "la_G", sizeof(double2) * K * 4 * blk * kchunk);
         double2* C = (double2*)ws_get(ctx, "la_C", sizeof(double2) * nv * 4 * blk * kchunk);
-        std::vector<disco_solver_stats> st(blk);
+        std::vector<SrcSpec> hspec(blk), hspecg(blk);
+        std::vector<int> hlanes(blk);
+        std::vector<disco_solver_stats> st(nrhs_set);
         long long solves = 0, iters = 0;
         double worst = 0;
         int fb = 0, outer = 0;
         for (int ts = 0; ts < T; ts++) {
             if (!((tmask >> ts) & 1ULL)) continue;
-            for (int r0 = 0; r0 < nrhs_set; r0 += blk) {
-                const int n = std::min(blk, nrhs_set - r0);
-                std::vector<SrcSpec> spec(n);
-                for (int r = 0; r < n; r++) spec[r] = SrcSpec{1ULL << ts, (r0 + r) / 4, (r0 + r) % 4};
-                HIPCHK(hipMemcpyAsync(specd, spec.data(), sizeof(SrcSpec) * n, hipMemcpyHostToDevice, ctx->stream));
-                k_sources<<<grid_for(V * n), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, n);
-                HIPCHK(hipGetLastError());
-                disco::solve_native(ctx, nullptr, *P, n, b64, x64, st.data());
-                for (int r = 0; r < n; r++) {
-                    all_ok &= st[r].converged != 0;
-                    worst = std::max(worst, st[r].true_rel_residual);
+            // the source timeslice's 4 nv sources feed the lanes; each finished
+            // solution is projected on every sink timeslice
+            disco::LaneFeeder f;
+            f.total = nrhs_set;
+            f.load = [&](int lane, int j, int width) {
+                hspec[lane] = SrcSpec{1ULL << ts, j / 4, j % 4};
+                HIPCHK(hipMemcpyAsync(specd + lane, &hspec[lane], sizeof(SrcSpec), hipMemcpyHostToDevice, ctx->stream));
+                k_source_lane<<<grid_for(V), 256, 0, ctx->stream>>>(Vi, specd, b64, V, Vs, nv, width, lane);
+            };
+            f.store = [&](const std::vector<int>& lanes, const std::vector<int>& js, int width) {
+                const int m = (int)lanes.size();
+                for (int q = 0; q < m; q++) {
+                    hspecg[q] = SrcSpec{1ULL << ts, js[q] / 4, js[q] % 4};
+                    hlanes[q] = lanes[q];
                 }
-                iters += st[0].iters;
-                outer += st[0].outer_iters;
-                fb |= st[0].fallback_used;
-                solves += n;
+                HIPCHK(hipMemcpyAsync(specg, hspecg.data(), sizeof(SrcSpec) * m, hipMemcpyHostToDevice, ctx->stream));
+                HIPCHK(hipMemcpyAsync(laneg, hlanes.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+                k_gather_lanes<<<grid_for(12 * V * m), 256, 0, ctx->stream>>>(x64, xg, V, width, laneg, m);
                 for (int tk0 = 0; tk0 < T; tk0 += kchunk) {
                     const int nk = std::min(kchunk, T - tk0);
                     for (int kk = 0; kk < nk; kk++)
-                        k_slab<<<grid_for(Vs * 12 * n), 256, 0, ctx->stream>>>(x64, G + (long)kk * K * 4 * n, V, Vs,
-                                                                                n, tk0 + kk);
-                    zgemm_hn(ctx, Vi + (long)tk0 * K * nv, nv, K * nv, G, 4L * n, K * 4L * n, C, nv, 4 * n, (int)K, nk);
-                    k_tau_scatter_all<<<grid_for((long)nv * 4 * n * nk), 256, 0, ctx->stream>>>(
-                        C, specd, (double2*)tau_out, nv, n, ts, T, tk0, nk);
+                        k_slab<<<grid_for(Vs * 12 * m), 256, 0, ctx->stream>>>(xg, G + (long)kk * K * 4 * m, V, Vs,
+                                                                                m, tk0 + kk);
+                    zgemm_hn(ctx, Vi + (long)tk0 * K * nv, nv, K * nv, G, 4L * m, K * 4L * m, C, nv, 4 * m, (int)K, nk);
+                    k_tau_scatter_all<<<grid_for((long)nv * 4 * m * nk), 256, 0, ctx->stream>>>(
+                        C, specg, (double2*)tau_out, nv, m, ts, T, tk0, nk);
                 }
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipStreamSynchronize(ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));  // the host staging is reused by the next hand-over
+            };
+            iters += disco::solve_fed(ctx, nullptr, *P, blk, f, b64, x64, st.data());
+            int set_outer = 0;
+            for (int j = 0; j < nrhs_set; j++) {
+                all_ok &= st[j].converged != 0;
+                worst = std::max(worst, st[j].true_rel_residual);
+                fb |= st[j].fallback_used;
+                set_outer = std::max(set_outer, st[j].outer_iters);
             }
+            outer += set_outer;
+            solves += nrhs_set;
         }
         if (agg) {
             agg->iters = (int)std::min<long long>(iters, 2147483647LL);

@@ -350,6 +350,50 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
     s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
 }
 
+// A lane that takes a new right-hand side: x = 0 and r = b on the flagged lanes.
+__global__ void k_lane_restart(double2* __restrict__ x64, double2* __restrict__ r64, const double2* __restrict__ b64,
+                               long V, int n, const int* __restrict__ flag) {
+    const long tot = 12 * V * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(i % n);
+        if (!flag[r]) continue;
+        x64[i] = make_double2(0.0, 0.0);
+        r64[i] = b64[i];
+    }
+}
+
+// partial ||b||^2 -> the outer state of the flagged lanes, as at the start of a
+// solve; their Krylov process restarts at the next refresh (marked broken down)
+__global__ void k_sc_lane_start(const double2* part, int nparts, RhsScal* sc, const int* flag, double tol2) {
+    cd q[1];
+    fold<1>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x || !flag[blockIdx.x]) return;
+    RhsScal& s = sc[blockIdx.x];
+    s.bb = q[0].re;
+    s.rr = q[0].re;
+    s.gam = q[0].re;
+    s.outer_done = s.rr <= tol2 * s.bb ? 1 : 0;
+    s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
+    s.breakdown = 1;
+    s.active = 0;
+}
+
+// one right-hand side in the canonical layout [V][12] <-> lane r of a native FP64 block
+__global__ void k_lane_in(const double2* __restrict__ src, double2* __restrict__ b64, long V, int n, int r) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < 12 * V; i += (long)gridDim.x * blockDim.x) {
+        const long s = i / 12;
+        const int k = (int)(i - s * 12);
+        b64[((long)k * V + s) * n + r] = src[i];
+    }
+}
+__global__ void k_lane_out(const double2* __restrict__ x64, double2* __restrict__ dst, long V, int n, int r) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < 12 * V; i += (long)gridDim.x * blockDim.x) {
+        const long s = i / 12;
+        const int k = (int)(i - s * 12);
+        dst[i] = x64[((long)k * V + s) * n + r];
+    }
+}
+
 // after a reliable update: rho = <rhat, r>, the reference ||r||^2 for the next
 // update, and every unfinished lane active again
 __global__ void k_sc_ru_refresh(const double2* part, int nparts, RhsScal* sc) {
@@ -966,8 +1010,14 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
 // residual does not follow the recursive one, restart their Krylov process.
 // The inner vectors keep the scale 1/||b|| of the start.
 template <class IO>
-static void ru_solve(Work& w, const disco_solver_params& P, int prec, const double2* b64, double2* x64,
-                     const uint8_t* mask, disco_solver_stats* st) {
+//
+// With a feeder (continuous batching), a lane whose right-hand side has
+// converged hands its solution over at that update and takes the next one
+// from the queue, with a Krylov process of its own; st then has one entry per
+// right-hand side of the queue.
+static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b64, double2* x64,
+                     const uint8_t* mask, disco_solver_stats* st, disco::LaneFeeder* feed = nullptr,
+                     long long* block_iters = nullptr) {
     disco_ctx* ctx = w.ctx;
     const int n = w.n;
     const long V = w.V;
@@ -978,11 +1028,24 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, const doub
     void* efull = ws_get(ctx, "dc_e", nbp);
     const VecGeo g64 = vgeo(V, DISCO_F64, n);
     const double tol2 = P.tol * P.tol;
+    // queue state: lane -> right-hand side (-1 idle), and where each started
+    std::vector<int> lane_src(n, -1), lane_it0(n, 0), lane_up0(n, 0);
+    int next = 0;
+    if (feed) {
+        for (int r = 0; r < n; r++) {
+            if (next >= feed->total) break;
+            feed->load(r, next, n);
+            lane_src[r] = next++;
+        }
+    }
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
     norm2<IO64>(w, b64, g64);
     k_sc_outer<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, b64, r64, 0);
-    const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+    // with a queue the cap applies per wave of right-hand sides
+    const int waves = feed ? std::max(1, (feed->total + n - 1) / n) : 1;
+    const int max_iter =
+        (int)std::min<long long>(2000000000LL, (long long)(P.max_iter > 0 ? P.max_iter : 100000) * waves);
     const int check = P.check_every > 0 ? P.check_every : 2;
     const double delta = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-3);
     const bool eo = ctx->opt_eo && disco::eo_supported(ctx);
@@ -1032,16 +1095,71 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, const doub
     int outer = 0, stall = 0, it_best = 0;
     double last_worst = 1e300;
     const bool trace = getenv("DISCO_TRACE") != nullptr;
+    std::vector<int> done_at(w.n, 0);
+    int* dflag = feed ? (int*)ws_get(ctx, "ru_flag", sizeof(int) * n) : nullptr;
+    std::vector<int> hflag(n, 0);
+    // hand over the lanes whose right-hand side is finished (all lanes still
+    // holding one when final), with their statistics
+    auto hand_over = [&](int it, bool final, int fb) {
+        std::vector<int> lanes, js;
+        for (int r = 0; r < n; r++) {
+            if (lane_src[r] < 0 || (!final && !w.h[r].outer_done)) continue;
+            const int j = lane_src[r];
+            disco_solver_stats& q = st[j];
+            q.iters = it - lane_it0[r];
+            q.outer_iters = std::max(1, outer - lane_up0[r]);
+            q.fallback_used = fb;
+            q.true_rel_residual = w.h[r].bb > 0 ? std::sqrt(w.h[r].rr / w.h[r].bb) : 0.0;
+            q.converged = q.true_rel_residual <= P.tol;
+            lanes.push_back(r);
+            js.push_back(j);
+            lane_src[r] = -1;
+        }
+        if (!lanes.empty()) feed->store(lanes, js, n);
+        return lanes;
+    };
     std::function<bool(int)> refresh = [&](int it) -> bool {
         fold_in();
         outer++;
+        if (feed) {
+            // finished lanes hand over and take the next right-hand sides
+            const std::vector<int> freed = hand_over(it, false, 0);
+            bool refill = false;
+            std::fill(hflag.begin(), hflag.end(), 0);
+            for (int r : freed) {
+                if (next >= feed->total) continue;
+                feed->load(r, next, n);
+                lane_src[r] = next++;
+                lane_it0[r] = it;
+                lane_up0[r] = outer;
+                hflag[r] = 1;
+                refill = true;
+            }
+            if (refill) {
+                HIPCHK(hipMemcpyAsync(dflag, hflag.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+                hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n, dflag);
+                norm2<IO64>(w, b64, g64);
+                k_sc_lane_start<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
+                pull(w);
+                // a new right-hand side starts the progress measure afresh
+                last_worst = 1e300;
+                stall = 0;
+            }
+        }
         bool open = false;
         double worst = 0;
         for (auto& s : w.h) {
             open |= !s.outer_done;
-            if (s.bb > 0) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+            if (s.bb > 0 && !s.outer_done) worst = std::max(worst, std::sqrt(s.rr / s.bb));
         }
-        if (trace) fprintf(stderr, "[disco] reliable update %d: worst true rel residual %.3e\n", outer, worst);
+        if (trace) {
+            fprintf(stderr, "[disco] reliable update %d at iteration %d: worst true rel residual %.3e\n", outer, it,
+                    worst);
+            for (int i = 0; i < w.n; i++)
+                if (w.h[i].outer_done && !done_at[i]) fprintf(stderr, "[disco] lane %d done at iteration %d\n", i, it);
+        }
+        for (int i = 0; i < w.n; i++)
+            if (w.h[i].outer_done && !done_at[i]) done_at[i] = it;
         if (!open) return false;
         if (worst > 0.5 * last_worst) {
             stall++;
@@ -1078,7 +1196,19 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, const doub
     int total = iters;
     if (!done && P.fallback) {
         fb = 1;
-        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, max_iter - iters), check, &total);
+        const int cap = P.max_iter > 0 ? P.max_iter : 100000;
+        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, feed ? cap : max_iter - iters), check, &total);
+    }
+    if (block_iters) *block_iters = total;
+    if (feed) {
+        hand_over(total, true, fb);
+        // right-hand sides the queue never reached (the solve gave up first)
+        if (next < feed->total) k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+        for (int j = next; j < feed->total; j++) {
+            st[j] = disco_solver_stats{0, 0, fb, 0, 1.0};
+            feed->store(std::vector<int>{0}, std::vector<int>{j}, n);  // x = 0
+        }
+        return;
     }
     fill_stats(w, P, total, std::max(1, outer), fb, st);
 }
@@ -1342,9 +1472,9 @@ static void cgnr_solve(Work& w, const disco_solver_params& P, const double2* b64
 
 namespace disco {
 
-// Solve on native FP64 blocks b64 -> x64 (n right-hand sides).
-void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
-                  double2* x64, disco_solver_stats* st) {
+// Per-block solver state: scalars, partial sums (up to 4 quantities per
+// right-hand side: the stencil's four-sum epilogue, FGMRES dots), cleared.
+static Work make_work(disco_ctx* ctx, int n) {
     Work w;
     w.ctx = ctx;
     w.n = n;
@@ -1352,10 +1482,53 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
     w.nsb = stencil_nsb(ctx, n);
     w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
     VecGeo g = vgeo(ctx->V, DISCO_F64, n);
-    size_t slots = (size_t)std::max(w.nsb, g.nb);
-    // up to 4 quantities per right-hand side (the stencil epilogues use 3, FGMRES dots 4)
+    size_t slots = (size_t)std::max(std::max(w.nsb, stencil_nsb(ctx, n, true)), g.nb);
     w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 4 * n);
     HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
+    return w;
+}
+
+// Every right-hand side of the queue f through a block of (at most) n lanes.
+// BICGSTAB_RU keeps the lanes busy: a converged lane takes the next right-hand
+// side at the update that finds it converged.  The other methods solve the
+// queue block by block.  st (host) receives f.total entries; returns the
+// inner iterations the block ran.
+long long solve_fed(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, LaneFeeder& f,
+                    double2* b64, double2* x64, disco_solver_stats* st) {
+    if (f.total <= 0) return 0;
+    n = std::min(n, f.total);
+    const uint8_t* mask = dom ? dom->d_mask : nullptr;
+    if (P.method == DISCO_BICGSTAB_RU && (P.inner_prec == DISCO_F32 || P.inner_prec == DISCO_BF16)) {
+        Work w = make_work(ctx, n);
+        long long it = 0;
+        if (P.inner_prec == DISCO_F32)
+            ru_solve<IO32>(w, P, DISCO_F32, b64, x64, mask, st, &f, &it);
+        else
+            ru_solve<IOBF>(w, P, DISCO_BF16, b64, x64, mask, st, &f, &it);
+        return it;
+    }
+    long long it = 0;
+    std::vector<disco_solver_stats> bst(n);
+    for (int j0 = 0; j0 < f.total; j0 += n) {
+        const int m = std::min(n, f.total - j0);
+        std::vector<int> lanes(m), js(m);
+        for (int r = 0; r < m; r++) {
+            f.load(r, j0 + r, m);
+            lanes[r] = r;
+            js[r] = j0 + r;
+        }
+        solve_native(ctx, dom, P, m, b64, x64, bst.data());
+        for (int r = 0; r < m; r++) st[j0 + r] = bst[r];
+        it += bst[0].iters;
+        f.store(lanes, js, m);
+    }
+    return it;
+}
+
+// Solve on native FP64 blocks b64 -> x64 (n right-hand sides).
+void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params& P, int n, const double2* b64,
+                  double2* x64, disco_solver_stats* st) {
+    Work w = make_work(ctx, n);
     const uint8_t* mask = dom ? dom->d_mask : nullptr;
     if (P.method == DISCO_CGNR_F64) {
         cgnr_solve(w, P, b64, x64, mask, st);
@@ -1372,9 +1545,9 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
         fgmres_solve(w, P, b64, x64, mask, st);
     } else if (P.method == DISCO_BICGSTAB_RU) {
         if (P.inner_prec == DISCO_F32)
-            ru_solve<IO32>(w, P, DISCO_F32, b64, x64, mask, st);
+            ru_solve<IO32>(w, P, DISCO_F32, const_cast<double2*>(b64), x64, mask, st);
         else if (P.inner_prec == DISCO_BF16)
-            ru_solve<IOBF>(w, P, DISCO_BF16, b64, x64, mask, st);
+            ru_solve<IOBF>(w, P, DISCO_BF16, const_cast<double2*>(b64), x64, mask, st);
         else
             disco_throw(DISCO_EINVAL, "reliable updates need FP32 or BF16 inner precision, not %d", P.inner_prec);
     } else {
@@ -1483,20 +1656,28 @@ extern "C" int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, c
         activate(ctx);
         if (nrhs == 0) return;
         const int blk = disco::default_rhs_block(*p, nrhs, ctx);
-        const size_t field = (size_t)ctx->V * 12 * sizeof(double2);
-        std::vector<disco_solver_stats> st(blk);
-        for (int r0 = 0; r0 < nrhs; r0 += blk) {
-            int n = std::min(blk, nrhs - r0);
-            size_t nb64 = disco::native_bytes(ctx, DISCO_F64, n);
-            double2* b64 = (double2*)ws_get(ctx, "solve_b64", nb64);
-            double2* x64 = (double2*)ws_get(ctx, "solve_x64", nb64);
-            disco::to_native(ctx, DISCO_F64, n, (const char*)b + r0 * field, b64);
-            disco::solve_native(ctx, dom, *p, n, b64, x64, st.data());
-            disco::from_native(ctx, DISCO_F64, n, x64, (char*)x + r0 * field);
-            for (int i = 0; i < n; i++) {
-                if (stats) stats[r0 + i] = st[i];
-                all_ok &= st[i].converged != 0;
-            }
+        const long V = ctx->V;
+        const size_t nb64 = disco::native_bytes(ctx, DISCO_F64, blk);
+        double2* b64 = (double2*)ws_get(ctx, "solve_b64", nb64);
+        double2* x64 = (double2*)ws_get(ctx, "solve_x64", nb64);
+        const double2* bc = (const double2*)b;
+        double2* xc = (double2*)x;
+        disco::LaneFeeder f;
+        f.total = nrhs;
+        f.load = [&](int lane, int j, int width) {
+            hipLaunchKernelGGL(k_lane_in, dim3(site_grid(V, 12)), dim3(256), 0, ctx->stream, bc + (size_t)j * 12 * V,
+                               b64, V, width, lane);
+        };
+        f.store = [&](const std::vector<int>& lanes, const std::vector<int>& js, int width) {
+            for (size_t q = 0; q < lanes.size(); q++)
+                hipLaunchKernelGGL(k_lane_out, dim3(site_grid(V, 12)), dim3(256), 0, ctx->stream, x64,
+                                   xc + (size_t)js[q] * 12 * V, V, width, lanes[q]);
+        };
+        std::vector<disco_solver_stats> st(nrhs);
+        disco::solve_fed(ctx, dom, *p, blk, f, b64, x64, st.data());
+        for (int i = 0; i < nrhs; i++) {
+            if (stats) stats[i] = st[i];
+            all_ok &= st[i].converged != 0;
         }
         HIPCHK(hipStreamSynchronize(ctx->stream));
     });

@@ -148,20 +148,22 @@ def plain_oracle():
     return pre, U, A, Vo, cut, oracle.loops(tau_f, CODES), oracle.loops(tau_b, CODES), tau_f, tau_b
 
 
-@pytest.mark.parametrize("method", ["CGNR_F64", "BICGSTAB_DC"])
-def test_end_to_end_plain_workload(disco, plain_oracle, method):
+@pytest.mark.parametrize("method,blk", [("CGNR_F64", 8), ("BICGSTAB_DC", 8), ("BICGSTAB_RU", 8), ("BICGSTAB_RU", 5)])
+def test_end_to_end_plain_workload(disco, plain_oracle, method, blk):
     """4^4 plain workload: the GPU computes its own eigenvectors, solves to 1e-12
     (full operator and packed block solves), and its loops and full, factorised
-    and subtracted correlators agree with the oracle's to 1e-10."""
+    and subtracted correlators agree with the oracle's to 1e-10.  With reliable
+    updates the lanes take the sources of every timeslice from one queue (a
+    block of 5 lanes does not divide the 16 sources of a timeslice)."""
     pre, U, A, Vo, cut, Lf_o, Lb_o, tau_f_o, tau_b_o = plain_oracle
     dims = pre.dims
-    _say("end-to-end", method)
+    _say("end-to-end", method, blk)
     ctx = _ctx(disco, dims, U, pre.kappa, pre.csw)
     if pre.ape_steps:
         ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
     Vg, _ = ctx.laplace_eigvecs(pre.nv, 1e-13)
     dom = ctx.domains(cut)
-    P = ctx.params(method=getattr(disco, method), tol=1e-12, inner_prec=disco.F32, rhs_block=8)
+    P = ctx.params(method=getattr(disco, method), tol=1e-12, inner_prec=disco.F32, rhs_block=blk)
     Lf, tf, st = ctx.loops_distill(Vg, CODES, P, None, want_tau=True)
     Lb, tb, stb = ctx.loops_distill(Vg, CODES, P, dom, want_tau=True)
     # packing: 2 temporal layers -> half as many block solves as logical sources
@@ -327,7 +329,8 @@ def test_slab_schedule_loops(disco, delta):
             assert err < 1e-9, (omega, g, err)
 
 
-def test_connected_correlator_and_noise_reduced_estimator(disco):
+@pytest.mark.parametrize("method,blk", [("BICGSTAB_DC", 12), ("BICGSTAB_RU", 5)])
+def test_connected_correlator_and_noise_reduced_estimator(disco, method, blk):
     """All-to-all perambulators on the GPU and the connected contraction (the
     sink-to-source direction from gamma_5-hermiticity) against the oracle,
     which takes both directions from direct solves; C^NR = C^(c) + dC and the
@@ -347,7 +350,7 @@ def test_connected_correlator_and_noise_reduced_estimator(disco):
     ctx = _ctx(disco, dims, U, kappa, csw)
     ctx.ape_smear(2, 0.5)
     Vg, lam_g = ctx.laplace_eigvecs(3, 1e-13)
-    P = ctx.params(method=disco.BICGSTAB_DC, tol=1e-12, inner_prec=disco.F32, rhs_block=12)
+    P = ctx.params(method=getattr(disco, method), tol=1e-12, inner_prec=disco.F32, rhs_block=blk)
     tau_g, st = ctx.perambulators_all(Vg, P)
     assert ctx.last_solves() == T * 12
     C = ctx.connected(tau_g, codes).cpu().numpy()

@@ -281,3 +281,43 @@ def test_reliable_updates_fallback_and_errors(disco, plain):
     with pytest.raises(disco.DiscoError) as e:
         ctx.solve_multi_rhs(ctx.dev(b), ctx.params(method=disco.BICGSTAB_RU, tol=1e-10, inner_prec=disco.F64))
     assert e.value.code == disco.EINVAL
+
+
+@pytest.mark.parametrize("inner", ["F32", "BF16"])
+def test_reliable_updates_lane_refill(disco, inner):
+    """Eleven right-hand sides (one of them zero) through 3 lanes: a lane whose
+    right-hand side converges takes the next one at that update.  Every solution
+    meets the tolerance by the oracle's FP64 residual, with the residual the
+    library reports, and matches the solution of an 11-lane block (no refill) to
+    the accuracy both solves reach; the zero right-hand side gives x = 0."""
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.124, 1.2
+    U = synth.gauge_field(dims, 0.3, 71)
+    A = oracle.clover(U, dims, kappa, csw)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, csw)
+    b = synth.random_spinor(ctx.V, 11, 72)
+    b[4] = 0
+    b[7] *= 1e-3  # a differently scaled right-hand side
+    tol = 1e-12 if inner == "F32" else 1e-10
+    sol = {}
+    for blk in (3, 11):
+        P = ctx.params(method=disco.BICGSTAB_RU, tol=tol, inner_prec=getattr(disco, inner), rhs_block=blk)
+        x, st = ctx.solve_multi_rhs(ctx.dev(b), P)
+        x = x.cpu().numpy()
+        sol[blk] = x
+        assert np.abs(x[4]).max() == 0
+        live = [k for k in range(11) if k != 4]
+        rr = _true_rel_res(U, A, dims, kappa, b[live], x[live])
+        _say("  refill %s block %d: iterations per rhs %s, oracle residual %.2e" %
+             (inner, blk, [s.iters for s in st], rr.max()))
+        assert rr.max() <= tol * 1.05
+        assert all(s.fallback_used == 0 and s.converged for s in st)
+        for q, k in enumerate(live):
+            assert abs(rr[q] - st[k].true_rel_residual) <= max(1e-2 * rr[q], 2e-15)
+    for k in range(11):
+        if k == 4:
+            continue
+        d = np.linalg.norm(sol[3][k] - sol[11][k]) / np.linalg.norm(sol[11][k])
+        assert d < 1e4 * tol, (k, d)  # a lane mix-up would show at O(1)
