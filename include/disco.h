@@ -79,7 +79,10 @@ enum {
                             * inner_tol (default 3e-2 for BF16, 1e-3 for FP32) the corrections
                             * are folded into the FP64 solution, the FP64 true residual replaces
                             * the recursive one and the process continues (lanes that break
-                            * down or stall restart it); even-odd as for BICGSTAB_DC */
+                            * down or stall restart it); even-odd as for BICGSTAB_DC.  The
+                            * right-hand sides of a call form one queue: a lane whose right-hand
+                            * side has converged takes the next one at that update, so no lane
+                            * waits for the slowest of its block */
 };
 
 /* ---------------------------------------------------------------- context */
@@ -191,7 +194,8 @@ typedef struct {
 } disco_solver_params;
 
 typedef struct {
-    int iters;              /* inner Krylov iterations */
+    int iters;              /* inner Krylov iterations (BICGSTAB_RU: those of this right-hand
+                             * side's lane while it held it; otherwise its block's) */
     int outer_iters;        /* defect-correction cycles (1 for CGNR) */
     int fallback_used;      /* 1 when the FP64 fallback ran */
     int converged;          /* 1 when true_rel_residual <= tol */
@@ -253,9 +257,10 @@ int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double*
  * one multi-site source and solved together (exact, because D_Lambda does not
  * couple different layers: the multi-site sources of the Cost section).
  * Vev device [T][nv][Vs][3]; w device or NULL; L device [ngamma][T]; tau_out
- * device [T][nv][4][nv][4] or NULL; agg (host, may be NULL) gets the summed
- * iterations and the worst true residual.  T <= 64.  ENOCONV if any solve
- * misses p->tol. */
+ * device [T][nv][4][nv][4] or NULL; agg (host, may be NULL) gets the inner
+ * iterations the solver's block ran in all, the most outer cycles (or
+ * reliable updates) one right-hand side took, and the worst true residual.
+ * T <= 64.  ENOCONV if any solve misses p->tol. */
 int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vev, int nv, const double* w,
                         const int* gammas, int ngamma, const disco_solver_params* p, void* L, void* tau_out,
                         disco_solver_stats* agg);
