@@ -182,8 +182,8 @@ typedef struct {
     int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */
     double inner_tol;  /* relative reduction asked of each inner solve (e.g. 1e-5) */
     int rhs_block;     /* right-hand sides per batched launch; 0 = the autotuned block for
-                        * inner_prec if disco_autotune ran, else 16; clamped to 64 and to
-                        * the plane limit given under disco_autotune */
+                        * inner_prec if disco_autotune ran (at most 32 for BICGSTAB_DC), else
+                        * 16; clamped to 64 and to the plane limit given under disco_autotune */
     int fallback;      /* 1: on inner breakdown/stagnation continue with FP64 CGNR */
     int check_every;   /* iterations between host convergence checks (0 = default: 2 for
                         * BICGSTAB_DC, whose inner solves first run, without checks, as many
@@ -339,9 +339,10 @@ int disco_effective_mass(const double* C, int n, double* meff);
 
 /* Autotuner: time a fixed number of inner BiCGStab iterations (FP32 or BF16
  * storage, the full operator when dom is NULL) for right-hand-side blocks of
- * 4, 8, 16 and 32 on device-generated random sources, and keep the block with
+ * 8, 16, 32 and 64 on device-generated random sources, and keep the block with
  * the lowest cost per right-hand side and iteration for later solves with
- * rhs_block = 0.  best (host) receives it; cost_us (host, 4 entries, may be
+ * rhs_block = 0 (BICGSTAB_DC uses at most 32 of it: its fixed blocks wait for
+ * their slowest member, while BICGSTAB_RU refills finished lanes).  best (host) receives it; cost_us (host, 4 entries, may be
  * NULL) the measured microseconds per right-hand side and iteration, 0 for a
  * block not tried.  A block is tried only if one spinor plane of it
  * (V * block * 16 bytes at every precision) stays below 4 GiB, the limit of

@@ -490,7 +490,7 @@ class Context:
         cost = np.zeros(4, dtype=np.float64)
         self._chk(lib().disco_autotune(self.h, None if dom is None else dom.h, int(inner_prec), ctypes.byref(best),
                                        cost.ctypes.data_as(P)))
-        return best.value, {k: c for k, c in zip((4, 8, 16, 32), cost) if c > 0}
+        return best.value, {k: c for k, c in zip((8, 16, 32, 64), cost) if c > 0}
 
     def last_solves(self):
         return int(lib().disco_last_solves(self.h))

@@ -1558,8 +1558,12 @@ void solve_native(disco_ctx* ctx, const disco_domains* dom, const disco_solver_p
 int default_rhs_block(const disco_solver_params& P, int nrhs, const disco_ctx* ctx) {
     int b = P.rhs_block;
     if (b <= 0 && ctx && (P.method == DISCO_BICGSTAB_DC || P.method == DISCO_BICGSTAB_RU) && P.inner_prec >= 0 &&
-        P.inner_prec <= 2)
+        P.inner_prec <= 2) {
         b = ctx->tuned_block[P.inner_prec];
+        // fixed blocks (defect correction) run until their slowest member is
+        // done; beyond 32 lanes that idle time outweighs the cheaper iterations
+        if (P.method == DISCO_BICGSTAB_DC) b = std::min(b, 32);
+    }
     if (b <= 0) b = 16;
     return std::max(1, std::min({b, nrhs, 64, max_rhs_block(ctx)}));
 }
@@ -1588,7 +1592,7 @@ extern "C" int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inne
         REQUIRE(ctx->have_clover, DISCO_ESTATE, "autotune before clover_setup");
         REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
         activate(ctx);
-        const int cand[4] = {4, 8, 16, 32};
+        const int cand[4] = {8, 16, 32, 64};
         const int iters = 20;
         double cost[4] = {0, 0, 0, 0};
         hipEvent_t e0, e1;
