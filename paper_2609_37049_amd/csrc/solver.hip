@@ -37,7 +37,8 @@ namespace {
 struct RhsScal {
     cd rho, alpha, omega, beta;
     double rr, bb, irr, ibb, gam, scale;
-    int active, breakdown, outer_done, pad;
+    int active, breakdown, outer_done;
+    int reached;  // reliable updates: the inner residual has fallen by inner_tol since the last update
     double best;  // smallest inner ||r||^2 since it last halved (reliable updates)
     int since;    // inner iterations since then
     int pad2;
@@ -340,7 +341,7 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
         s.rr = q[0].re;
     }
     if (mode == 2) {
-        if (!s.outer_done && !s.active && !s.breakdown && s.rr > 0.5 * s.gam) s.breakdown = 1;
+        if (!s.outer_done && (s.reached || !s.active) && !s.breakdown && s.rr > 0.5 * s.gam) s.breakdown = 1;
         s.gam = s.rr;
         if (s.rr <= tol2 * s.bb) s.outer_done = 1;
         if (s.outer_done) s.scale = 0.0;
@@ -350,15 +351,15 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
     s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
 }
 
-// A lane that takes a new right-hand side: x = 0 and r = b on the flagged lanes.
+// Lanes that take new right-hand sides (lanes[0..m)): x = 0 and r = b there.
 __global__ void k_lane_restart(double2* __restrict__ x64, double2* __restrict__ r64, const double2* __restrict__ b64,
-                               long V, int n, const int* __restrict__ flag) {
-    const long tot = 12 * V * n;
+                               long V, int n, const int* __restrict__ lanes, int m) {
+    const long tot = 12 * V * m;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
-        const int r = (int)(i % n);
-        if (!flag[r]) continue;
-        x64[i] = make_double2(0.0, 0.0);
-        r64[i] = b64[i];
+        const long row = i / m;
+        const long j = row * n + lanes[i - row * m];
+        x64[j] = make_double2(0.0, 0.0);
+        r64[j] = b64[j];
     }
 }
 
@@ -375,6 +376,7 @@ __global__ void k_sc_lane_start(const double2* part, int nparts, RhsScal* sc, co
     s.outer_done = s.rr <= tol2 * s.bb ? 1 : 0;
     s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
     s.breakdown = 1;
+    s.reached = 0;
     s.active = 0;
 }
 
@@ -407,6 +409,7 @@ __global__ void k_sc_ru_refresh(const double2* part, int nparts, RhsScal* sc) {
     s.best = q[1].re;
     s.since = 0;
     s.breakdown = 0;
+    s.reached = 0;
     s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
     s.alpha = s.omega = s.beta = mk(0.0, 0.0);
 }
@@ -422,6 +425,7 @@ __global__ void k_sc_bicg_init(const double2* part, int nparts, RhsScal* sc) {
     s.ibb = q[0].re;
     s.best = q[0].re;
     s.since = 0;
+    s.reached = 0;
     s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
     s.breakdown = 0;
     s.alpha = s.omega = s.beta = mk(0.0, 0.0);
@@ -472,7 +476,7 @@ __global__ void k_sc_bicg_omega_beta(const double2* part, int nparts, RhsScal* s
 // stall > 0, a lane whose ||r|| has not halved within stall iterations stops
 // and is marked as broken down (reliable updates then restart its Krylov
 // process; defect correction starts its next cycle).
-__global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, double tol2, int stall) {
+__global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, double tol2, int stall, double hard2) {
     cd q[1];
     fold<1>(part, blockIdx.x, nparts, q);
     if (threadIdx.x) return;
@@ -480,7 +484,10 @@ __global__ void k_sc_bicg_conv(const double2* part, int nparts, RhsScal* sc, dou
     if (!s.active) return;
     s.irr = q[0].re;
     if (s.irr <= tol2 * s.ibb) {
-        s.active = 0;
+        // with hard2 > 0 (reliable updates) the lane is marked and iterates on
+        // until the next update, or until it has fallen by hard2 as well
+        s.reached = 1;
+        if (hard2 <= 0 || s.irr <= hard2 * s.ibb) s.active = 0;
         return;
     }
     if (!(s.irr <= 1e12 * s.best)) {
@@ -667,7 +674,7 @@ static void op_apply(Work& w, const InnerOp& op, int prec, const void* in, void*
 template <class IO>
 static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void* e, const uint8_t* mask,
                     double inner_tol, int max_iter, int check_every, int hint = 0,
-                    const std::function<bool(int)>* refresh = nullptr, int stall = 0) {
+                    const std::function<bool(int)>* refresh = nullptr, int stall = 0, double hard2 = 0.0) {
     disco_ctx* ctx = w.ctx;
     const long Vfull = w.V;
     w.V = op.Vv;  // vector helpers below work on the operator's vectors
@@ -698,15 +705,16 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
                  disco::EPI_DOTAUX | disco::EPI_NORM | disco::EPI_DOTIN | disco::EPI_DOTAUXIN, tmp);
         k_sc_bicg_omega_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_xrp<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, v, r, g, w.sc, w.part);
-        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2, stall);
+        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2, stall, hard2);
     };
     // A chunk of check_every iterations is captured once as a graph and replayed
     // between the host's convergence reads (eager when profiling or disabled).
     hipGraphExec_t exec = nullptr;
     if (ctx->opt_graphs && !ctx->prof_on && check_every > 1) {
         char key[512];
-        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g/%d", prec, w.n, check_every,
-                 op.eo ? 1 : 0, (void*)mask, r, rh, p, v, s, t, e, tmp, (void*)w.sc, (void*)w.part, tol2, stall);
+        snprintf(key, sizeof(key), "bicg/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%p/%g/%d/%g", prec, w.n,
+                 check_every, op.eo ? 1 : 0, (void*)mask, r, rh, p, v, s, t, e, tmp, (void*)w.sc, (void*)w.part, tol2,
+                 stall, hard2);
         auto itg = ctx->graphs.find(key);
         if (itg != ctx->graphs.end()) {
             exec = itg->second;
@@ -754,13 +762,18 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
         }
         pull(w);
         if (refresh) {
-            bool open = false, need = false;
+            // an update when a lane has stopped (breakdown, stall, its hard
+            // limit), or when a quarter of the open lanes have fallen by inner_tol
+            bool need = false;
+            int nopen = 0, nreached = 0;
             for (auto& sc : w.h) {
                 if (sc.outer_done) continue;
-                open = true;
+                nopen++;
+                nreached += sc.reached != 0;
                 need |= sc.active == 0;
             }
-            if (!open) break;
+            if (!nopen) break;
+            need |= nreached >= std::max(1, nopen / 4);
             if (need) {
                 w.V = Vfull;
                 const bool more = (*refresh)(it);
@@ -1097,7 +1110,8 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     const bool trace = getenv("DISCO_TRACE") != nullptr;
     std::vector<int> done_at(w.n, 0);
     int* dflag = feed ? (int*)ws_get(ctx, "ru_flag", sizeof(int) * n) : nullptr;
-    std::vector<int> hflag(n, 0);
+    int* dlane = feed ? (int*)ws_get(ctx, "ru_lane", sizeof(int) * n) : nullptr;
+    std::vector<int> hflag(n, 0), hlane(n, 0);
     // hand over the lanes whose right-hand side is finished (all lanes still
     // holding one when final), with their statistics
     auto hand_over = [&](int it, bool final, int fb) {
@@ -1136,8 +1150,12 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
                 refill = true;
             }
             if (refill) {
+                int m = 0;
+                for (int r = 0; r < n; r++)
+                    if (hflag[r]) hlane[m++] = r;
                 HIPCHK(hipMemcpyAsync(dflag, hflag.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
-                hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n, dflag);
+                HIPCHK(hipMemcpyAsync(dlane, hlane.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+                hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n, dlane, m);
                 norm2<IO64>(w, b64, g64);
                 k_sc_lane_start<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
                 pull(w);
@@ -1183,7 +1201,9 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         HIPCHK(hipGetLastError());
         return true;
     };
-    const int iters = bicg_run<IO>(w, op, prec, rhat, ee, mask, delta, max_iter, check, 0, &refresh, kRuStall);
+    // a marked lane iterates on until the update, but no further than delta^2
+    const int iters =
+        bicg_run<IO>(w, op, prec, rhat, ee, mask, delta, max_iter, check, 0, &refresh, kRuStall, delta * delta * delta * delta);
     pull(w);
     bool done = true;
     for (auto& s : w.h) done &= s.outer_done != 0;
