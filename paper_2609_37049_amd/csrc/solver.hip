@@ -47,6 +47,9 @@ struct RhsScal {
 // inner iterations without a halving of a lane's inner residual before it
 // stops (its Krylov process then restarts)
 constexpr int kRuStall = 100;
+// threads of a per-RHS scalar step (one block per right-hand side folds its
+// partial sums; more threads keep more loads in flight)
+constexpr int kScalarBlock = 1024;
 
 // --------------------------------------------------------------- vector units
 // One "unit" is the widest natural load of a storage format: 1 complex
@@ -598,7 +601,7 @@ static void stencil(Work& w, int prec, int dag, const void* in, void* out, const
 static void outer_residual(Work& w, const double2* b64, const double2* x64, double2* r64, const uint8_t* mask,
                            double tol2) {
     stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
-    k_sc_outer<<<w.n, 256, 0, w.ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
+    k_sc_outer<<<w.n, kScalarBlock, 0, w.ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
 }
 
 // FP64 CGNR on D e = rhs (e starts at 0) to relative residual tol.  Uses and
@@ -616,19 +619,19 @@ static void cgnr_run(Work& w, const double2* rhs, double2* e, const uint8_t* mas
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(e, g.total);
     copy_scale<IO64, IO64>(w, rhs, r, 0);
     norm2<IO64>(w, r, g);
-    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, 0, tol2);
+    k_sc_outer<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g.nb, w.sc, 0, tol2);
     stencil(w, DISCO_F64, 1, r, z, nullptr, nullptr, mask, disco::EPI_NORM);
-    k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 0, tol2);
+    k_sc_cgnr<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, z, p, 0);
     int it = 0;
     while (it < max_iter) {
         for (int k = 0; k < check_every && it < max_iter; k++, it++) {
             stencil(w, DISCO_F64, 0, p, q, nullptr, nullptr, mask, disco::EPI_NORM);
-            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
+            k_sc_cgnr<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 1, tol2);
             hipLaunchKernelGGL(k_cgnr_xr, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, q, r, g, w.sc, w.part);
-            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, 2, tol2);
+            k_sc_cgnr<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g.nb, w.sc, 2, tol2);
             stencil(w, DISCO_F64, 1, r, z, nullptr, nullptr, mask, disco::EPI_NORM);
-            k_sc_cgnr<<<w.n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 3, tol2);
+            k_sc_cgnr<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 3, tol2);
             hipLaunchKernelGGL(k_cgnr_p, dim3(g.nb), dim3(g.bd), 0, ctx->stream, p, z, g, w.sc);
         }
         HIPCHK(hipGetLastError());
@@ -692,20 +695,20 @@ static int bicg_run(Work& w, const InnerOp& op, int prec, const void* rin, void*
     copy_scale<IO, IO>(w, rin, rh, 0);
     copy_scale<IO, IO>(w, rin, p, 0);
     norm2<IO>(w, r, g);
-    k_sc_bicg_init<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc);
+    k_sc_bicg_init<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g.nb, w.sc);
     const double tol2 = inner_tol * inner_tol;
     // one BiCGStab iteration: 2 operator applications with fused reductions
     // (the second one's four sums give omega and beta), 2 vector passes
     // (s, then x, r and p together), 3 scalar steps
     auto iteration = [&]() {
         op_apply(w, op, prec, p, v, rh, mask, disco::EPI_DOTAUX, tmp);
-        k_sc_bicg_alpha<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
+        k_sc_bicg_alpha<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_s<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, r, v, s, g, w.sc);
         op_apply(w, op, prec, s, t, rh, mask,
                  disco::EPI_DOTAUX | disco::EPI_NORM | disco::EPI_DOTIN | disco::EPI_DOTAUXIN, tmp);
-        k_sc_bicg_omega_beta<<<w.n, 256, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
+        k_sc_bicg_omega_beta<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, op.nsb, w.sc);
         hipLaunchKernelGGL(k_bicg_xrp<IO>, dim3(g.nb), dim3(g.bd), 0, ctx->stream, e, p, s, t, v, r, g, w.sc, w.part);
-        k_sc_bicg_conv<<<w.n, 256, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2, stall, hard2);
+        k_sc_bicg_conv<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g.nb, w.sc, tol2, stall, hard2);
     };
     // A chunk of check_every iterations is captured once as a graph and replayed
     // between the host's convergence reads (eager when profiling or disabled).
@@ -945,7 +948,7 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
     const double tol2 = P.tol * P.tol;
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
     norm2<IO64>(w, b64, g64);
-    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    k_sc_outer<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, b64, r64, 0);
     int iters = 0, outer = 0;
     const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
@@ -1053,7 +1056,7 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     }
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
     norm2<IO64>(w, b64, g64);
-    k_sc_outer<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, b64, r64, 0);
     // with a queue the cap applies per wave of right-hand sides
     const int waves = feed ? std::max(1, (feed->total + n - 1) / n) : 1;
@@ -1096,7 +1099,7 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         reconstruct();
         dc_update<IO>(w, x64, efull);
         stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
-        k_sc_outer<<<n, 256, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 2, tol2);
+        k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 2, tol2);
         pull(w);
     };
     InnerOp op;
@@ -1135,8 +1138,10 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     std::function<bool(int)> refresh = [&](int it) -> bool {
         fold_in();
         outer++;
-        if (feed) {
-            // finished lanes hand over and take the next right-hand sides
+        // finished lanes hand over and take the next right-hand sides; again
+        // while a new one is finished at once (a zero right-hand side)
+        for (bool again = feed != nullptr; again;) {
+            again = false;
             const std::vector<int> freed = hand_over(it, false, 0);
             bool refill = false;
             std::fill(hflag.begin(), hflag.end(), 0);
@@ -1157,11 +1162,12 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
                 HIPCHK(hipMemcpyAsync(dlane, hlane.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
                 hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n, dlane, m);
                 norm2<IO64>(w, b64, g64);
-                k_sc_lane_start<<<n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
+                k_sc_lane_start<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
                 pull(w);
                 // a new right-hand side starts the progress measure afresh
                 last_worst = 1e300;
                 stall = 0;
+                for (int r = 0; r < n; r++) again |= hflag[r] && w.h[r].outer_done;
             }
         }
         bool open = false;
@@ -1197,7 +1203,7 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         void* p = ws_get(ctx, "bi_p", nbp);
         hipLaunchKernelGGL(k_ru_refresh<IO>, dim3(gh.nb), dim3(gh.bd), 0, ctx->stream, r, rhat, p, rh, ee, gh, w.sc,
                            w.part);
-        k_sc_ru_refresh<<<n, 256, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
+        k_sc_ru_refresh<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
         HIPCHK(hipGetLastError());
         return true;
     };
@@ -1421,7 +1427,7 @@ static void fgmres_solve(Work& w, const disco_solver_params& P, const double2* b
     const double tol2 = P.tol * P.tol;
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
     norm2<IO64>(w, b64, g64);
-    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    k_sc_outer<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, b64, r64, 0);
     int iters = 0, outer = 0;
     const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
@@ -1472,7 +1478,7 @@ static void cgnr_solve(Work& w, const disco_solver_params& P, const double2* b64
     const int check = P.check_every > 0 ? P.check_every : 10;
     k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
     norm2<IO64>(w, b64, g64);
-    k_sc_outer<<<w.n, 256, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+    k_sc_outer<<<w.n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
     copy_scale<IO64, IO64>(w, b64, r64, 0);
     int iters = 0, outer = 0;
     // restarted from the true residual until it meets tol (a restart costs one

@@ -285,11 +285,11 @@ def test_reliable_updates_fallback_and_errors(disco, plain):
 
 @pytest.mark.parametrize("inner", ["F32", "BF16"])
 def test_reliable_updates_lane_refill(disco, inner):
-    """Eleven right-hand sides (one of them zero) through 3 lanes: a lane whose
+    """Eleven right-hand sides (four of them zero) through 3 lanes: a lane whose
     right-hand side converges takes the next one at that update.  Every solution
     meets the tolerance by the oracle's FP64 residual, with the residual the
     library reports, and matches the solution of an 11-lane block (no refill) to
-    the accuracy both solves reach; the zero right-hand side gives x = 0."""
+    the accuracy both solves reach; zero right-hand sides give x = 0."""
     dims = (8, 8, 8, 8)
     kappa, csw = 0.124, 1.2
     U = synth.gauge_field(dims, 0.3, 71)
@@ -299,6 +299,7 @@ def test_reliable_updates_lane_refill(disco, inner):
     ctx.clover_setup(kappa, csw)
     b = synth.random_spinor(ctx.V, 11, 72)
     b[4] = 0
+    b[8:] = 0  # zero right-hand sides finish at once, also at the end of the queue
     b[7] *= 1e-3  # a differently scaled right-hand side
     tol = 1e-12 if inner == "F32" else 1e-10
     sol = {}
@@ -307,8 +308,9 @@ def test_reliable_updates_lane_refill(disco, inner):
         x, st = ctx.solve_multi_rhs(ctx.dev(b), P)
         x = x.cpu().numpy()
         sol[blk] = x
-        assert np.abs(x[4]).max() == 0
-        live = [k for k in range(11) if k != 4]
+        for k in (4, 8, 9, 10):
+            assert np.abs(x[k]).max() == 0
+        live = [k for k in range(11) if k not in (4, 8, 9, 10)]
         rr = _true_rel_res(U, A, dims, kappa, b[live], x[live])
         _say("  refill %s block %d: iterations per rhs %s, oracle residual %.2e" %
              (inner, blk, [s.iters for s in st], rr.max()))
@@ -317,7 +319,7 @@ def test_reliable_updates_lane_refill(disco, inner):
         for q, k in enumerate(live):
             assert abs(rr[q] - st[k].true_rel_residual) <= max(1e-2 * rr[q], 2e-15)
     for k in range(11):
-        if k == 4:
+        if k in (4, 8, 9, 10):
             continue
         d = np.linalg.norm(sol[3][k] - sol[11][k]) / np.linalg.norm(sol[11][k])
         assert d < 1e4 * tol, (k, d)  # a lane mix-up would show at O(1)
