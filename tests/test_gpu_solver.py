@@ -148,16 +148,18 @@ def test_graph_replays_equal_eager(disco):
     V = int(np.prod(dims))
     b = ctx.dev(synth.random_spinor(V, 24, 22))
     out = {}
-    cases = [(m, i) for m in (disco.BICGSTAB_DC, disco.BICGSTAB_RU) for i in (disco.F32, disco.BF16)]
+    # (method, inner precision, lanes): 3 lanes refill from the queue of 24
+    cases = [(m, i, 8) for m in (disco.BICGSTAB_DC, disco.BICGSTAB_RU) for i in (disco.F32, disco.BF16)]
+    cases += [(disco.BICGSTAB_RU, disco.BF16, 3)]
     for g in (0, 1):
         ctx.set_option(disco.OPT_GRAPHS, g)
-        for m, inner in cases:
-            P = ctx.params(method=m, tol=1e-11, inner_prec=inner, rhs_block=8, check_every=5)
+        for m, inner, blk in cases:
+            P = ctx.params(method=m, tol=1e-11, inner_prec=inner, rhs_block=blk, check_every=5)
             x, st = ctx.solve_multi_rhs(b, P)
-            out[(g, m, inner)] = (x.cpu().numpy(), [s.iters for s in st], [s.outer_iters for s in st])
-    for m, inner in cases:
-        assert out[(0, m, inner)][1:] == out[(1, m, inner)][1:]
-        assert np.array_equal(out[(0, m, inner)][0], out[(1, m, inner)][0])
+            out[(g, m, inner, blk)] = (x.cpu().numpy(), [s.iters for s in st], [s.outer_iters for s in st])
+    for key in cases:
+        assert out[(0,) + key][1:] == out[(1,) + key][1:]
+        assert np.array_equal(out[(0,) + key][0], out[(1,) + key][0])
     ctx.set_option(disco.OPT_GRAPHS, 1)
 
 
