@@ -54,9 +54,9 @@ def main():
     torch.cuda.synchronize()
     if args.solver_iters > 0 and prec != d.F64:
         ctx.set_option(d.OPT_GRAPHS, 0)
-        g = torch.Generator().manual_seed(5)
-        b = torch.complex(torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64),
-                          torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64)).cuda()
+        g = torch.Generator(device="cuda").manual_seed(5)
+        b = torch.complex(torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64, device="cuda"),
+                          torch.randn((n, ctx.V, 4, 3), generator=g, dtype=torch.float64, device="cuda"))
         P = ctx.params(method=d.BICGSTAB_RU, tol=1e-10, max_iter=args.solver_iters, inner_prec=prec,
                        rhs_block=n, fallback=0, check_every=args.solver_iters)
         ctx.solve_multi_rhs(b, P, allow_noconv=True)
