@@ -40,10 +40,17 @@ __device__ __forceinline__ E ld_at(const void* b, size_t plane_bytes, unsigned o
     const char* base = (const char*)b + plane_bytes;
     return *(const E*)(base + off);
 }
-template <typename E>
+// NT: a streaming (non-temporal) store, for outputs that the same launch
+// never reads again, so that they do not displace reused inputs from L2.
+template <bool NT = false, typename E>
 __device__ __forceinline__ void st_at(void* b, size_t plane_bytes, unsigned off, E v) {
     char* base = (char*)b + plane_bytes;
-    *(E*)(base + off) = v;
+    if constexpr (NT) {
+        typedef unsigned wv __attribute__((ext_vector_type(sizeof(E) / 4)));
+        __builtin_nontemporal_store(__builtin_bit_cast(wv, v), (wv*)(base + off));
+    } else {
+        *(E*)(base + off) = v;
+    }
 }
 
 // Buffer-resource loads: one descriptor (wave-uniform, scalar registers) for a
@@ -87,11 +94,12 @@ struct IO64 {
             p[k] = mk(v.x, v.y);
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
         const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
         const size_t ps = (size_t)V * n * 16;
 #pragma unroll
-        for (int k = 0; k < 12; k++) st_at(b, k * ps, off, make_double2(p[k].re, p[k].im));
+        for (int k = 0; k < 12; k++) st_at<NT>(b, k * ps, off, make_double2(p[k].re, p[k].im));
     }
     template <bool BUF>
     __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
@@ -146,12 +154,13 @@ struct IO32 {
             p[2 * k + 1] = mk(v.z, v.w);
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
         const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
         const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 6; k++)
-            st_at(b, k * ps, off, make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im));
+            st_at<NT>(b, k * ps, off, make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im));
     }
     template <bool BUF>
     __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
@@ -237,12 +246,13 @@ struct IOBF {
         f2v f = {c.re, c.im};
         return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, b2v));
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(void* b, long V, int n, int r, int s, const cx<T> p[12]) {
         const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
         const size_t ps = (size_t)V * n * 16;
 #pragma unroll
         for (int k = 0; k < 3; k++)
-            st_at(b, k * ps, off, make_uint4(pack(p[4 * k]), pack(p[4 * k + 1]), pack(p[4 * k + 2]), pack(p[4 * k + 3])));
+            st_at<NT>(b, k * ps, off, make_uint4(pack(p[4 * k]), pack(p[4 * k + 1]), pack(p[4 * k + 2]), pack(p[4 * k + 3])));
     }
     __device__ __forceinline__ static void load_link(const LinkT* U, long V, int mu, int s, cx<T> u[9]) {
         IO32::load_link(U, V, mu, s, u);

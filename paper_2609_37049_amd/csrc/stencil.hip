@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
                 for (int k = 0; k < 12; k++) o[k] = b[k] - o[k];
             }
         }
-        IO::store(a.out, Vv, n, r, sv, o);
+        IO::template store<true>(a.out, Vv, n, r, sv, o);
         int q = 0;
         cx<T> w[12];
         if (EPI & (disco::EPI_DOTAUX | disco::EPI_DOTAUXIN)) IO::template loadv<BUF>(a.aux2, Vv, n, r, sv, w);
@@ -434,7 +434,7 @@ __global__ void k_to_native(const double2* __restrict__ in, void* __restrict__ o
 #pragma unroll
         for (int k = 0; k < 12; k++) p[k] = mk((float)q[k].x, (float)q[k].y);
     }
-    IO::store(out, V, nr, r, s, p);
+    IO::template store<true>(out, V, nr, r, s, p);
 }
 
 template <class IO>
