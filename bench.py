@@ -1,18 +1,21 @@
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--method ru|dc]
+                    [--workload prec_16x16x16x32|batch_24x24x24x48] [--no-cpu-baseline]
 
-Workload: the mixed-precision distillation set-up on a 16^3 x 32 lattice
-(synthetic links exp(i 0.25 sum r_a T_a), 5 APE steps alpha = 0.5 for the
-Laplacian, Wilson-clover kappa = 0.125, csw = 1.5, antiperiodic time, Nv = 32
-eigenvectors per timeslice, domains 4^3 x 8), solved to true relative residual
-1e-10 by BiCGStab with FP32-arithmetic inner solves inside FP64 defect
-correction.
+Workload (default): the mixed-precision distillation set-up on a 16^3 x 32
+lattice (synthetic links exp(i 0.25 sum r_a T_a), 5 APE steps alpha = 0.5 for
+the Laplacian, Wilson-clover kappa = 0.125, csw = 1.5, antiperiodic time,
+Nv = 32 eigenvectors per timeslice, domains 4^3 x 8), solved to true relative
+residual 1e-10 by BiCGStab with BF16-stored, FP32-arithmetic inner solves and
+FP64 reliable updates (--method dc: inside FP64 defect correction).
+--workload batch_24x24x24x48 runs the same step on the 24^3 x 48 batching
+shape (kappa = 0.126, csw = 1.6, Nv = 64, domains 6 x 6 x 8 x 12).
 
 One step is one batch of the whole hot path: the four timeslices of one
-multi-site packing set (one timeslice per temporal layer of the 4^3 x 8
-partition) -- sources, full-operator solves (4 x 4 x 32 = 512 RHS), packed
-domain-restricted solves (128 solves carrying 512 logical RHS), perambulator
+multi-site packing set (one timeslice per temporal layer of the partition) --
+sources, full-operator solves (4 x 4 x Nv RHS), packed domain-restricted
+solves (4 x Nv solves carrying 4 x 4 x Nv logical RHS), perambulator
 projection, loops for five Gamma channels, and the full / factorised /
 subtracted correlators.  The value is logical RHS (full + restricted) per
 second over the timed steps; set-up (clover term, APE, eigenvectors) is timed
@@ -245,9 +248,9 @@ def cpu_baseline(pre, seconds_budget=30.0):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / dt, "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": "1 full-operator RHS of the 16^3x32 workload: oracle FP64 CGNR to true rel. residual "
+            "sample": "1 full-operator RHS of the %s workload: oracle FP64 CGNR to true rel. residual "
                       "1e-10 (%d iterations, %.1f s) + its projection at the source timeslice; source = one "
-                      "normalised Gaussian colour vector on timeslice 0 in spin 0" % (it, dt)}
+                      "normalised Gaussian colour vector on timeslice 0 in spin 0" % ("x".join(map(str, dims)), it, dt)}
 
 
 def main():
@@ -261,6 +264,7 @@ def main():
                     help="BiCGStab with reliable updates (default) or inside FP64 defect correction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the stencil measurement at 24^3x48")
+    ap.add_argument("--workload", choices=["prec_16x16x16x32", "batch_24x24x24x48"], default="prec_16x16x16x32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solves of different right-hand sides are independent, so "
@@ -272,7 +276,7 @@ def main():
     import synth
     import paper_2609_37049_amd as d
 
-    pre = synth.PRESETS["prec_16x16x16x32"]
+    pre = synth.PRESETS[args.workload]
     dims = pre.dims
     T = dims[3]
     codes = [d.G_1, d.G_5, d.G_X, d.G_Y, d.G_Z]
@@ -292,6 +296,7 @@ def main():
     tuned, tune_cost = ctx.autotune(inner)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    print("set-up done in %.1f s (rhs block %d)" % (setup_s, tuned), file=sys.stderr, flush=True)
 
     method = d.BICGSTAB_RU if args.method == "ru" else d.BICGSTAB_DC
     P = ctx.params(method=method, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block)
@@ -366,10 +371,13 @@ def main():
     sites = ctx.V // 2 if "_eo" in kernel_tag else ctx.V
     print("profiled step done: %d launches of %s" % (nl, kernel_tag), file=sys.stderr, flush=True)
     blk = args.rhs_block or tuned
-    roof = stencil_roofline(kernel_tag, nl, ms, by, sites, blk, "%s/n%d" % (kernel_tag, blk))
+    lat = "x".join(map(str, dims))
+    big = args.workload != "prec_16x16x16x32"
+    roof = stencil_roofline(kernel_tag, nl, ms, by, sites, blk, "%s/n%d" % (kernel_tag, blk) + ("/" + lat if big else ""))
     comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
     slab = slab_schedule_cost(ctx, d, Vev, inner, args.rhs_block or tuned, method)
-    large = None if args.no_large else stencil_at_batch_shape(d, inner, blk)
+    # the stencil at the batching shape (already the workload's own shape when big)
+    large = None if (args.no_large or big) else stencil_at_batch_shape(d, inner, blk)
     if large:
         print("24^3x48 stencil: %.1f GB/s over %d launches" % (large["achieved"], large["launches_timed"]),
               file=sys.stderr, flush=True)
@@ -378,10 +386,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "16^3x32 Wilson-clover kappa=0.125 csw=1.5, Nv=32, domains 4^3x8, "
+        "config": {"workload": "%s Wilson-clover kappa=%g csw=%g, Nv=%d, domains %s, "
                                "BiCGStab %s-storage/FP32 inner, %s, to FP64 true residual 1e-10" % (
+                                   lat, pre.kappa, pre.csw, nv, "x".join(map(str, pre.block)),
                                    args.inner, "reliable updates" if args.method == "ru" else "FP64 defect correction"),
-                   "lattice": "16x16x16x32", "nv": nv, "rhs_block": args.rhs_block or tuned,
+                   "lattice": lat, "nv": nv, "rhs_block": args.rhs_block or tuned,
                    "autotune_us_per_rhs_iter": {str(k): round(v, 3) for k, v in tune_cost.items()},
                    "inner_storage": args.inner, "hip_graphs": True, "method": args.method,
                    "outer": "f64", "logical_rhs_per_step": rhs // max(args.steps, 1),
