@@ -66,6 +66,8 @@ struct Unit<IO64> {
     __device__ __forceinline__ static void st(void* p, long i, const cx<double> c[1]) {
         ((double2*)p)[i] = make_double2(c[0].re, c[0].im);
     }
+    // the values as st then ld would return them
+    __device__ __forceinline__ static void rnd(cx<double>*) {}
 };
 template <>
 struct Unit<IO32> {
@@ -78,6 +80,7 @@ struct Unit<IO32> {
     __device__ __forceinline__ static void st(void* p, long i, const cx<float> c[2]) {
         ((float4*)p)[i] = make_float4(c[0].re, c[0].im, c[1].re, c[1].im);
     }
+    __device__ __forceinline__ static void rnd(cx<float>*) {}
 };
 template <>
 struct Unit<IOBF> {
@@ -91,6 +94,14 @@ struct Unit<IOBF> {
     }
     __device__ __forceinline__ static void st(void* p, long i, const cx<float> c[4]) {
         ((uint4*)p)[i] = make_uint4(IOBF::pack(c[0]), IOBF::pack(c[1]), IOBF::pack(c[2]), IOBF::pack(c[3]));
+    }
+    // round to BF16 (nearest even) in registers
+    __device__ __forceinline__ static void rnd(cx<float> c[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t w = IOBF::pack(c[k]);
+            c[k] = mk(bf2f(w & 0xffffu), bf2f(w >> 16));
+        }
     }
 };
 
@@ -211,8 +222,8 @@ __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, c
             rn[c] = s[c] - om * t[c];
         }
         U::st(x_, i, x);
+        U::rnd(rn);  // the stored (rounded) residual feeds p and the norm
         U::st(r_, i, rn);
-        U::ld(r_, i, rn);  // the stored (rounded) residual feeds p and the norm
 #pragma unroll
         for (int c = 0; c < U::C; c++) {
             p[c] = rn[c] + be * (p[c] - om * v[c]);
@@ -301,12 +312,32 @@ __global__ void k_cgnr_p(double2* p, const double2* z, VecGeo g, const RhsScal* 
 
 // --------------------------------------------------------------- scalar steps
 // Each block folds the partial sums of one right-hand side in a fixed order.
+// Each thread issues the loads of U slots before adding them (in slot order,
+// so the sums are the same as one slot at a time): the fold is bound by load
+// latency, and one block per right-hand side has few waves to hide it.
 template <int NQ>
 __device__ __forceinline__ void fold(const double2* part, long r, int nparts, cd out[NQ]) {
+    constexpr int U = NQ >= 4 ? 4 : 8;
     double acc[2 * NQ];
 #pragma unroll
     for (int k = 0; k < 2 * NQ; k++) acc[k] = 0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    const int bd = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * bd < nparts; i += U * bd) {
+        double2 v[U][NQ];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < NQ; q++) v[u][q] = part[(r * NQ + q) * nparts + i + u * bd];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                acc[2 * q] += v[u][q].x;
+                acc[2 * q + 1] += v[u][q].y;
+            }
+    }
+    for (; i < nparts; i += bd) {
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
             double2 v = part[(r * NQ + q) * nparts + i];
