@@ -244,8 +244,15 @@ constexpr int kStageCloverBytes = 18 * 16;   // 2 blocks x 9 float4
 
 // MASK = false: the full operator (every hop present, no mask load; the hop
 // tests are uniform).  MASK = true: hops removed where the domain mask says so.
+// Blocks per CU the compiler must fit: six (six waves per SIMD, at most 80
+// VGPRs) for the hot BF16 even-odd instances with buffer loads and staged
+// links, which fit without spilling; no constraint for the others.
+template <class IO, bool BUF, bool STAGE, bool EO>
+struct MinBlocks {
+    static constexpr int v = (EO && BUF && STAGE && sizeof(typename IO::T) == 4 && IO::planes == 3) ? 6 : 1;
+};
 template <class IO, int EPI, bool BUF, bool STAGE, bool EO, bool MASK>
-__global__ __launch_bounds__(kStencilBlock) void k_dslash(const StencilArgs a) {
+__global__ __launch_bounds__(kStencilBlock, (MinBlocks<IO, BUF, STAGE, EO>::v)) void k_dslash(const StencilArgs a) {
     typedef typename IO::T T;
     constexpr int NQ = EpiCount<EPI>::nq;
     const int n = a.n;
