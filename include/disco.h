@@ -96,7 +96,9 @@ int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out
 int disco_destroy(disco_ctx* ctx);
 /* Issue all later work on `hip_stream` (a hipStream_t; NULL = null stream). */
 int disco_set_stream(disco_ctx* ctx, void* hip_stream);
-/* Message for the last error on ctx (never NULL; "" when none). */
+/* Message for the last error on ctx (never NULL; "" when none).  With
+ * ctx = NULL: the message of the last failed disco_create on the calling
+ * thread, or "null context" when there was none. */
 const char* disco_last_error(const disco_ctx* ctx);
 
 /* ---------------------------------------------------------------- gauge / clover setup

@@ -323,6 +323,9 @@ __global__ void k_clover_expand(const double2* __restrict__ A64, long V, double2
 // ----------------------------------------------------------------- C ABI
 extern "C" {
 
+// Message of the last failed disco_create on this thread (its context is gone).
+static thread_local std::string create_err;
+
 int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out) {
     if (!out || !dims || !bc) return DISCO_EINVAL;
     *out = nullptr;
@@ -346,6 +349,7 @@ int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out
         disco::build_traversal(ctx);
     });
     if (rc != DISCO_OK) {
+        create_err = ctx->err;
         delete ctx;
         return rc;
     }
@@ -385,7 +389,10 @@ int disco_set_stream(disco_ctx* ctx, void* s) {
     return DISCO_OK;
 }
 
-const char* disco_last_error(const disco_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* disco_last_error(const disco_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    return create_err.empty() ? "null context" : create_err.c_str();
+}
 
 int disco_gauge_set(disco_ctx* ctx, const void* U, int where) {
     if (!ctx) return DISCO_EINVAL;
