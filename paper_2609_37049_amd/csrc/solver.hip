@@ -859,6 +859,46 @@ __global__ void k_eo_merge(const void* __restrict__ he, const void* __restrict__
         IO::store(full, V, n, r, (int)st, p);
     }
 }
+// k_copy_scale (FP64 -> inner precision, times scale[r]) and k_eo_split in
+// one pass: the scaled residual goes straight to its even and odd halves.
+template <class IO>
+__global__ void k_scale_split(const double2* __restrict__ full, void* __restrict__ he, void* __restrict__ ho, long V,
+                              int n, const RhsScal* __restrict__ sc, int Lx, int Ly, int Lz) {
+    typedef typename IO::T T;
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long st = j / n;
+        const int r = (int)(j - st * n);
+        const double f = sc[r].scale;
+        cx<double> a[12];
+        cx<T> b[12];
+        IO64::load(full, V, n, r, (int)st, a);
+#pragma unroll
+        for (int k = 0; k < 12; k++) b[k] = mk((T)(f * a[k].re), (T)(f * a[k].im));
+        IO::store(parity_of(st, Lx, Ly, Lz) ? ho : he, V / 2, n, r, (int)(st >> 1), b);
+    }
+}
+// k_eo_merge and k_dc_update in one pass: x64 += (1/scale[r]) e with e read
+// from its even and odd halves (same lanes skipped as k_dc_update).
+template <class IO>
+__global__ void k_dc_update_eo(double2* __restrict__ x64, const void* __restrict__ he, const void* __restrict__ ho,
+                               long V, int n, const RhsScal* __restrict__ sc, int Lx, int Ly, int Lz) {
+    const long tot = V * n;
+    for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
+        const long st = j / n;
+        const int r = (int)(j - st * n);
+        if (sc[r].outer_done || sc[r].breakdown == 2) continue;
+        const double f = sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0;
+        cx<typename IO::T> a[12];
+        cx<double> x[12];
+        IO::load(parity_of(st, Lx, Ly, Lz) ? ho : he, V / 2, n, r, (int)(st >> 1), a);
+        IO64::load(x64, V, n, r, (int)st, x);
+#pragma unroll
+        for (int k = 0; k < 12; k++) x[k] = mk(x[k].re + f * (double)a[k].re, x[k].im + f * (double)a[k].im);
+        IO64::store(x64, V, n, r, (int)st, x);
+    }
+}
+
 // out = A^-1 in on the half vector of parity par (site-local)
 template <class IO>
 __global__ void k_eo_clover_inv(const void* __restrict__ in, void* __restrict__ out, const void* __restrict__ Ai,
@@ -1107,28 +1147,32 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     void* ee = eo ? ws_get(ctx, "eo_ee", hb) : efull;
     void* eodd = eo ? ws_get(ctx, "eo_eo", hb) : nullptr;
     const void* Ai = prec == DISCO_F64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32;
-    // rin (full lattice) -> rhat: the inner system's source
+    // scale[r] r64 -> rhat, the inner system's source (in even-odd form the
+    // scaled residual is split into re, ro on the way, without a full-lattice copy)
     auto prepare = [&]() {
-        if (!eo) return;
-        hipLaunchKernelGGL(k_eo_split<IO>, dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, rin, re, ro, V, n, Lx,
-                           Ly, Lz);
+        if (!eo) {
+            copy_scale<IO64, IO>(w, r64, rin, 1);
+            return;
+        }
+        hipLaunchKernelGGL(k_scale_split<IO>, dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, r64, re, ro, V, n,
+                           w.sc, Lx, Ly, Lz);
         hipLaunchKernelGGL(k_eo_clover_inv<IO>, dim3(site_grid(V / 2, n)), dim3(256), 0, ctx->stream, ro, uo, Ai, V,
                            n, 1, Lx, Ly, Lz);
         disco::StencilCall cp{prec, 0, n, uo, rhat, re, nullptr, mask, nullptr, disco::EPI_NONE, 0, 0.0, 1.0, k};
         disco::stencil_launch(ctx, cp);
     };
-    // ee -> efull (odd sites from the source the correction belongs to)
-    auto reconstruct = [&]() {
-        if (!eo) return;
-        disco::StencilCall cr{prec, 0, n, ee, eodd, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
-        disco::stencil_launch(ctx, cr);
-        hipLaunchKernelGGL(k_eo_merge<IO>, dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, ee, eodd, efull, V, n,
-                           Lx, Ly, Lz);
-    };
-    // fold the correction into x64 and recompute the FP64 true residual
+    // fold the correction into x64 (in even-odd form its odd half is first
+    // reconstructed from the source it belongs to, and both halves are read
+    // in place) and recompute the FP64 true residual
     auto fold_in = [&]() {
-        reconstruct();
-        dc_update<IO>(w, x64, efull);
+        if (eo) {
+            disco::StencilCall cr{prec, 0, n, ee, eodd, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
+            disco::stencil_launch(ctx, cr);
+            hipLaunchKernelGGL((k_dc_update_eo<IO>), dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, x64, ee,
+                               eodd, V, n, w.sc, Lx, Ly, Lz);
+        } else {
+            dc_update<IO>(w, x64, efull);
+        }
         stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
         k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 2, tol2);
         pull(w);
@@ -1137,7 +1181,6 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     op.eo = eo;
     op.Vv = Vv;
     op.nsb = disco::stencil_nsb(ctx, n, eo);
-    copy_scale<IO64, IO>(w, r64, rin, 1);
     prepare();
     int outer = 0, stall = 0, it_best = 0;
     double last_worst = 1e300;
@@ -1226,7 +1269,6 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         // no halving of the worst true residual over 8 updates and 800
         // iterations (lanes restart on their own after 100): leave it to the fallback
         if (stall >= 8 && it - it_best >= 800) return false;
-        copy_scale<IO64, IO>(w, r64, rin, 1);
         prepare();
         const VecGeo gh = vgeo(Vv, prec, n);
         void* r = ws_get(ctx, "bi_r", nbp);
