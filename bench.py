@@ -253,9 +253,10 @@ def cpu_baseline(pre, nrhs=2):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": nrhs / dt, "unit": "RHS/s", "cores": cores, "kind": "oracle",
             "sample": "%d full-operator RHS of the %s workload: oracle FP64 CGNR to true rel. residual "
-                      "1e-10 (%s iterations, %.1f s in all) + their projections at the source timeslice; "
-                      "sources = one normalised Gaussian colour vector on timeslice 0 in spins 0..%d"
-                      % (nrhs, "x".join(map(str, dims)), "+".join(map(str, its)), dt, nrhs - 1)}
+                      "1e-10 (%s iterations, %.1f s in all), each with its projection at the source timeslice; "
+                      "source = one normalised Gaussian colour vector on timeslice 0, in spin %s"
+                      % (nrhs, "x".join(map(str, dims)), "+".join(map(str, its)), dt,
+                         " and ".join(str(a) for a in range(nrhs)))}
 
 
 def main():
