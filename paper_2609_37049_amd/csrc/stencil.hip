@@ -532,8 +532,11 @@ int plane_rhs_limit(const disco_ctx* ctx) {
 // the order is x fastest, then y within a tile of yt rows, then t within the
 // slab, then z, then the y tiles: hops in t and z then land a few hundred
 // sites away in the visiting order (instead of a whole timeslice), so the
-// neighbours of the sites in flight are still in that XCD's L2.  DISCO_TRAVERSAL
-// = natural restores lexicographic order.
+// neighbours of the sites in flight are still in that XCD's L2.  yt is the
+// largest divisor of Ly with Lx * yt * (Lt/8) <= 320 sites per z step, but at
+// least 2 when Ly is even: single-row tiles send every y hop across a tile
+// (4, 2 and 2 rows at 16^3x32, 24^3x48 and 32^3x64).
+// DISCO_TRAVERSAL = natural restores lexicographic order.
 void build_traversal(disco_ctx* ctx) {
     const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2], Lt = ctx->dims[3];
     const long V = ctx->V;
@@ -556,6 +559,7 @@ void build_traversal(disco_ctx* ctx) {
         int yt = 1;
         for (int c = 1; c <= Ly; c++)
             if (Ly % c == 0 && (long)Lx * c * tc <= 320) yt = c;
+        if (yt == 1 && Ly % 2 == 0) yt = 2;
         for (int ch = 0; ch < nch; ch++)
             for (int yb = 0; yb < Ly / yt; yb++)
                 for (int z = 0; z < Lz; z++)
