@@ -935,9 +935,13 @@ __global__ void k_eo_clover_inv(const void* __restrict__ in, void* __restrict__ 
 // Inner solve D e = rin through the even-odd Schur complement:
 //   rhat = A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o),  M e_e = rhat (BiCGStab),
 //   e_o = A_oo^-1 (r_o + kappa H_oe e_e).
+// With r64 and x64 given (defect correction), rin = scale[r] r64 is split into
+// its halves straight from the FP64 residual, and the correction is folded
+// into x64 from its halves (x64 += e / scale[r]) instead of being merged into e.
 template <class IO>
 static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_t* mask, double inner_tol,
-                       int max_iter, int check_every, int hint = 0, int stall = 0) {
+                       int max_iter, int check_every, int hint = 0, int stall = 0, const double2* r64 = nullptr,
+                       double2* x64 = nullptr) {
     disco_ctx* ctx = w.ctx;
     const long V = w.V;
     const int n = w.n;
@@ -952,7 +956,11 @@ static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_
     const void* Ai = prec == DISCO_F64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32;
     const int grid = site_grid(V, n);
     const double k = ctx->kappa;
-    hipLaunchKernelGGL(k_eo_split<IO>, dim3(grid), dim3(256), 0, ctx->stream, rin, re, ro, V, n, Lx, Ly, Lz);
+    if (r64)
+        hipLaunchKernelGGL(k_scale_split<IO>, dim3(grid), dim3(256), 0, ctx->stream, r64, re, ro, V, n, w.sc, Lx, Ly,
+                           Lz);
+    else
+        hipLaunchKernelGGL(k_eo_split<IO>, dim3(grid), dim3(256), 0, ctx->stream, rin, re, ro, V, n, Lx, Ly, Lz);
     hipLaunchKernelGGL(k_eo_clover_inv<IO>, dim3(site_grid(V / 2, n)), dim3(256), 0, ctx->stream, ro, uo, Ai, V, n, 1,
                        Lx, Ly, Lz);
     disco::StencilCall cp{prec, 0, n, uo, rhat, re, nullptr, mask, nullptr, disco::EPI_NONE, 0, 0.0, 1.0, k};
@@ -964,7 +972,11 @@ static int bicg_run_eo(Work& w, int prec, const void* rin, void* e, const uint8_
     const int it = bicg_run<IO>(w, op, prec, rhat, ee, mask, inner_tol, max_iter, check_every, hint, nullptr, stall);
     disco::StencilCall cr{prec, 0, n, ee, eo, ro, nullptr, mask, nullptr, disco::EPI_NONE, 1, 0.0, 1.0, k};
     disco::stencil_launch(ctx, cr);
-    hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, ee, eo, e, V, n, Lx, Ly, Lz);
+    if (x64)
+        hipLaunchKernelGGL((k_dc_update_eo<IO>), dim3(grid), dim3(256), 0, ctx->stream, x64, ee, eo, V, n, w.sc, Lx, Ly,
+                           Lz);
+    else
+        hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, ee, eo, e, V, n, Lx, Ly, Lz);
     HIPCHK(hipGetLastError());
     return it;
 }
@@ -1056,21 +1068,22 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
         last_worst = std::min(last_worst, worst);
         if (stall >= 5 && iters - it_best >= 800) break;
         outer++;
-        copy_scale<IO64, IO>(w, r64, rin, 1);
         int ran;
         if (use_eo) {
-            ran = bicg_run_eo<IO>(w, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint,
-                                  kRuStall);
+            // scaled residual split and correction folded in by the inner solve
+            ran = bicg_run_eo<IO>(w, prec, nullptr, nullptr, mask, itol, std::min(inner_cap, max_iter - iters), check,
+                                  hint, kRuStall, r64, x64);
         } else {
+            copy_scale<IO64, IO>(w, r64, rin, 1);
             InnerOp op;
             op.Vv = w.V;
             op.nsb = w.nsb;
             ran = bicg_run<IO>(w, op, prec, rin, e, mask, itol, std::min(inner_cap, max_iter - iters), check, hint,
                                nullptr, kRuStall);
+            dc_update<IO>(w, x64, e);
         }
         iters += ran;
         hint = ran;
-        dc_update<IO>(w, x64, e);
         outer_residual(w, b64, x64, r64, mask, tol2);
     }
     int fb = 0;
