@@ -75,7 +75,8 @@ def stencil_roofline(kernel_tag, nl, ms, by, sites, blk, traffic_key):
     """HBM roofline of a stencil family from event-timed launches: algorithmic
     bytes over time against the HBM peak, with the calibrated counter traffic
     (when the committed entry matches the sources) and the vector-ALU rate
-    beside it.  The stencil saturates neither unit; HBM is the nearer bound."""
+    beside it.  The launches are bound on the memory side (L1 misses, each
+    paying the L2 round trip); neither the ALUs nor HBM saturate."""
     avg_ms = ms / max(nl, 1)
     gbps = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     tflops = FLOP_PER_SITE_RHS * sites * blk / (avg_ms / 1e3) / 1e12 if avg_ms > 0 else 0.0
