@@ -252,7 +252,36 @@ def cpu_baseline(pre, nrhs=2):
         its.append(it)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the oracle's operator alone, with all threads and with one: stencil GB/s by
+    # the same algorithmic-byte count as the GPU (FP64, one RHS: 1536 bytes per
+    # site), and the one-thread solve rate these give at the measured CGNR
+    # iterations (one D and one D^+ per iteration)
+    def apply_s(reps=3):
+        t = time.perf_counter()
+        for _ in range(reps):
+            oracle.dirac(U, A, dims, bc, pre.kappa, b)
+        return (time.perf_counter() - t) / reps
+    t_all = apply_s()
+    old = oracle.set_threads(1)
+    try:
+        t_one = apply_s()
+    finally:
+        oracle.set_threads(old)
+    bytes_apply = V * (48 * 8 + 72 * 8 + 72 * 8)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    mean_it = sum(its) / len(its)
     return {"value": nrhs / dt, "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "stencil_gbps": round(bytes_apply / t_all / 1e9, 2),
+            "one_thread": {"stencil_gbps": round(bytes_apply / t_one / 1e9, 3),
+                           "rhs_per_s_estimate": 1.0 / (2 * mean_it * t_one),
+                           "note": "D applications timed with one OpenMP thread; the RHS rate assumes the same "
+                                   "%.0f CGNR iterations (one D and one D^+ each)" % mean_it},
             "sample": "%d full-operator RHS of the %s workload: oracle FP64 CGNR to true rel. residual "
                       "1e-10 (%s iterations, %.1f s in all), each with its projection at the source timeslice; "
                       "source = one normalised Gaussian colour vector on timeslice 0, in spin %s"

@@ -73,6 +73,8 @@ def _lib():
         lib.orc_cgnr.argtypes = [P, P, P, P, D, P, I, P, P, D, I, P, P]
         lib.orc_cgnr.restype = I
         lib.orc_gamma.argtypes = [I, P]
+        lib.orc_set_threads.argtypes = [I]
+        lib.orc_set_threads.restype = I
         _lib_handle = lib
     return _lib_handle
 
@@ -126,6 +128,12 @@ def _cut_arg(cut, dims):
         return None, max(dims)
     c = np.ascontiguousarray(np.asarray(cut, dtype=np.uint8))
     return c, c.shape[1]
+
+
+def set_threads(n: int) -> int:
+    """Timing helper: OpenMP threads of later oracle calls (n > 0); returns the
+    previous maximum."""
+    return _lib().orc_set_threads(int(n))
 
 
 def dirac(U, A, dims, bc, kappa, psi, cut=None, dagger=False) -> np.ndarray:

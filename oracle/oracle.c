@@ -30,6 +30,7 @@
  * cut masks cut[mu*Lmax + x] = 1 when the face between x and x+1 (mod L_mu)
  * is a domain boundary.
  */
+#include <omp.h>
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
@@ -360,4 +361,12 @@ int orc_cgnr(const int d[4], const int bc[4], const cplx* U, const cplx* A, doub
     if (relres_out) *relres_out = rel;
     free(r); free(z); free(p); free(w);
     return status;
+}
+
+/* Timing helper (no arithmetic): set the OpenMP thread count of later calls
+ * when n > 0 and return the previous maximum. */
+int orc_set_threads(int n) {
+    const int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
 }

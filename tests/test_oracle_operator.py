@@ -235,3 +235,24 @@ def test_schur_factorisation_of_propagator():
     assert np.abs(Dinv[np.ix_(L, L)] - rhs).max() < 1e-12
     # the restricted operator really is the principal submatrix
     assert np.abs(Db[np.ix_(L, L)] - D[np.ix_(L, L)]).max() == 0
+
+
+def test_oracle_thread_count_does_not_change_results():
+    """The timing helper that runs the oracle on one thread changes no
+    arithmetic: D psi is the same bit for bit (sites are independent)."""
+    import numpy as np
+    import oracle
+    import synth
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    A = oracle.clover(U, dims, 0.12, 1.0)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((256, 4, 3)) + 1j * rng.standard_normal((256, 4, 3))
+    y_all = oracle.dirac(U, A, dims, (1, 1, 1, -1), 0.12, psi)
+    old = oracle.set_threads(1)
+    try:
+        assert old >= 1
+        y_one = oracle.dirac(U, A, dims, (1, 1, 1, -1), 0.12, psi)
+    finally:
+        assert oracle.set_threads(old) == 1
+    assert np.array_equal(y_all, y_one)
