@@ -258,3 +258,72 @@ def test_training_over_ensembles_generalises(disco):
         steps[name] = st[0].iters
     _say("  held-out ensemble: trained %d, untrained %d Arnoldi steps" % (steps["trained"], steps["untrained"]))
     assert steps["trained"] < steps["untrained"]
+
+
+# ---- at the size the benchmark runs the network (16^3 x 32)
+FULL = (16, 16, 16, 32)
+
+
+def _wilson_squared_weights(kappa, C=16):
+    W1 = np.zeros((nn.NOFF, C, 1, 4, 4), dtype=np.complex128)
+    W1[40, 1, 0] = np.eye(4)
+    W2 = np.zeros((nn.NOFF, C, C, 4, 4), dtype=np.complex128)
+    W3 = np.zeros((nn.NOFF, 1, C, 4, 4), dtype=np.complex128)
+    for W, o, i in ((W2, 2, 1), (W3, 0, 2)):
+        W[40, o, i] = np.eye(4)
+        for mu in range(4):
+            g = oracle.gamma(mu)
+            e = [0, 0, 0, 0]
+            e[mu] = 1
+            W[nn.offset_index(e), o, i] = -kappa * (np.eye(4) - g)
+            e[mu] = -1
+            W[nn.offset_index(e), o, i] = -kappa * (np.eye(4) + g)
+    return [W1, W2, W3]
+
+
+def test_delta_weights_give_wilson_squared_full_size(disco):
+    """The network with delta weights is D_W^2 (c_sw = 0) on the full 16^3 x 32
+    lattice of the benchmark, compared with the C oracle's operator applied
+    twice to the same two right-hand sides (8 per launch as in the solver)."""
+    kappa = 0.125
+    U = synth.gauge_field(FULL, 0.25, 2)
+    ctx = disco.Context(FULL, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, 0.0)
+    net = disco.Net(ctx, 16, 1)
+    net.set_weights(nn.pack_weights(_wilson_squared_weights(kappa)))
+    r = synth.random_spinor(ctx.V, 8, 34)
+    out = net.apply(ctx.dev(r)).cpu().numpy()
+    A = oracle.clover(U, FULL, kappa, 0.0)
+    for p in (0, 7):
+        ref = oracle.dirac(U, A, FULL, BC, kappa, oracle.dirac(U, A, FULL, BC, kappa, r[p]))
+        err = _rel(out[p], ref)
+        _say("net = D_W^2 at 16^3x32, rhs %d: rel L2 error %.2e" % (p, err))
+        assert err < 1e-2
+    net.close()
+
+
+def test_gauge_covariance_full_size(disco):
+    """With random weights on the full 16^3 x 32 lattice: N[U^g](g r) = g N[U](r)
+    for a random SU(3) transform g, to the BF16 accuracy of two applications
+    (each within 1.5e-2 of the exact network)."""
+    U = synth.gauge_field(FULL, 0.25, 2)
+    V = int(np.prod(FULL))
+    Om = synth.random_su3(V, 35)
+    ctx = disco.Context(FULL, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(0.125, 1.5)
+    net = disco.Net(ctx, 16, 1)
+    net.set_weights(nn.pack_weights(nn.init_weights(16, 36)))
+    r = synth.random_spinor(V, 2, 37)
+    out = net.apply(ctx.dev(r)).cpu().numpy()
+    ctx.gauge_set(oracle.gauge_transform(U, FULL, Om))
+    net.refresh()
+    rg = np.einsum("xab,pxsb->pxsa", Om, r)
+    outg = net.apply(ctx.dev(rg)).cpu().numpy()
+    for p in range(2):
+        ref = np.einsum("xab,xsb->xsa", Om, out[p])
+        err = _rel(outg[p], ref)
+        _say("gauge covariance at 16^3x32, rhs %d: rel L2 difference %.2e" % (p, err))
+        assert err < 3e-2
+    net.close()
