@@ -373,3 +373,54 @@ def test_connected_correlator_and_noise_reduced_estimator(disco, method, blk):
     m = ctx.effective_mass(C[1].real[: T // 2 + 1])
     ref = np.log(C[1].real[: T // 2] / C[1].real[1: T // 2 + 1])
     assert np.abs(m - ref).max() < 1e-14
+
+
+def test_bench_configuration_perambulators_sampled(disco):
+    """The benchmark's configuration on its full 16^3 x 32 workload: BF16-stored
+    BiCGStab with reliable updates, 64 lanes fed from one queue, projections of
+    the handed-over lanes; D on one timeslice (128 sources through 64 lanes)
+    and D_Lambda on one packing set (four timeslices per solve).  Sampled
+    columns tau(t,t)[:, :, i, alpha] against the oracle's own CGNR solves of
+    those sources (D_Lambda unpacked, one timeslice at a time).
+
+    Tolerance: both sides stop at a true relative residual (1e-10 here, 1e-11
+    for the oracle), so |tau - tau_ref| <= |D^-1| 1e-10 with unit sources; the
+    bound 1e-7 of max|tau_ref| allows |D^-1| up to 1e3 (observed: 1.6e-11 for
+    D, 3e-13 for D_Lambda).  Any wrong lane, source or sink timeslice gives an
+    error of order one."""
+    pre = synth.PRESETS["prec_16x16x16x32"]
+    dims = pre.dims
+    Lx, Ly, Lz, Lt = dims
+    Vs = Lx * Ly * Lz
+    nv = pre.nv
+    _say("bench configuration, sampled perambulators")
+    U = synth.gauge_field(dims, pre.eps, pre.seed)
+    ctx = _ctx(disco, dims, U, pre.kappa, pre.csw)
+    ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
+    Vev, _ = ctx.laplace_eigvecs(nv, 1e-11)
+    cut = synth.tiling_cuts(dims, pre.block)
+    dom = ctx.domains(cut)
+    P = ctx.params(method=disco.BICGSTAB_RU, tol=1e-10, inner_prec=disco.BF16, rhs_block=64)
+    t0 = 5
+    layer = pre.block[3]
+    tau_f = ctx.dev(np.zeros((Lt, nv, 4, nv, 4), dtype=np.complex128))
+    tau_b = ctx.dev(np.zeros((Lt, nv, 4, nv, 4), dtype=np.complex128))
+    ctx.perambulators_tt(Vev, 1 << t0, P, tau_f)
+    assert ctx.last_solves() == 4 * nv
+    pack = sum(1 << (t0 + layer * k) for k in range(Lt // layer))
+    ctx.perambulators_tt(Vev, pack, P, tau_b, dom)
+    assert ctx.last_solves() == 4 * nv   # four timeslices per packed solve
+    tf, tb = tau_f.cpu().numpy(), tau_b.cpu().numpy()
+    Vn = Vev.cpu().numpy()
+    A = oracle.clover(U, dims, pre.kappa, pre.csw)
+    for tau, c, ts in ((tf, None, (t0,)), (tb, cut, (t0, t0 + 2 * layer))):
+        for t in ts:
+            for i, a in ((0, 0), (nv - 1, 3)):
+                x, it, rr = oracle.cgnr(U, A, dims, BC, pre.kappa, oracle.source(Vn, dims, t, i, a), c, 1e-11)
+                ref = oracle.project(Vn, dims, x[None], t)[:, :, 0]
+                err = np.abs(tau[t, :, :, i, a] - ref).max() / np.abs(ref).max()
+                _say("  %s t=%d (i,alpha)=(%d,%d): %d oracle iterations, rel error %.2e" % (
+                    "D_Lambda" if c is not None else "D", t, i, a, it, err))
+                assert err < 1e-7
+    # timeslices outside the masks are not written
+    assert np.abs(tf[t0 + 1]).max() == 0 and np.abs(tb[t0 + 1]).max() == 0
