@@ -424,3 +424,21 @@ def test_bench_configuration_perambulators_sampled(disco):
                 assert err < 1e-7
     # timeslices outside the masks are not written
     assert np.abs(tf[t0 + 1]).max() == 0 and np.abs(tb[t0 + 1]).max() == 0
+    # the bench's loops and correlators on these perambulators, against the
+    # oracle's on the same tau (fixed-order traces and products)
+    Lf = ctx.loops(tau_f, CODES).cpu().numpy()
+    Lb = ctx.loops(tau_b, CODES).cpu().numpy()
+    for g, c in enumerate(CODES):
+        gm = oracle.channel_matrix(c)
+        for L, tau in ((Lf, tf), (Lb, tb)):
+            ref = np.array([oracle.loop_from_tau(tau[t], gm) for t in range(Lt)])
+            assert np.abs(L[g] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0), (c, g)
+        sg = _tilde_sign(c)
+        args = [ctx.dev(v[None]) for v in (Lf[g], sg * Lf[g], Lb[g], sg * Lb[g])]
+        C, Cf, dC, four = [x.cpu().numpy() for x in ctx.correlator(*args)]
+        rC, rCf, rdC, _ = oracle.correlator(Lf[g][None], sg * Lf[g][None], Lb[g][None], sg * Lb[g][None])
+        floor = 64 * np.finfo(float).eps * max(np.abs(Lf[g]).max(), np.abs(Lb[g]).max()) ** 2
+        tol = 1e-10 * np.abs(rC).max() + floor
+        for got, ref in ((C, rC), (Cf, rCf), (dC, rdC)):
+            assert np.abs(got - ref).max() <= tol, c
+        assert np.abs(four.sum(axis=0) - C).max() <= floor
