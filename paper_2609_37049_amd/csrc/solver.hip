@@ -95,6 +95,12 @@ struct Unit<IOBF> {
     __device__ __forceinline__ static void st(void* p, long i, const cx<float> c[4]) {
         ((uint4*)p)[i] = make_uint4(IOBF::pack(c[0]), IOBF::pack(c[1]), IOBF::pack(c[2]), IOBF::pack(c[3]));
     }
+    // streaming store, for vectors not read again before other traffic evicts them
+    __device__ __forceinline__ static void stnt(void* p, long i, const cx<float> c[4]) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        const u4 v = {IOBF::pack(c[0]), IOBF::pack(c[1]), IOBF::pack(c[2]), IOBF::pack(c[3])};
+        __builtin_nontemporal_store(v, (u4*)p + i);
+    }
     // round to BF16 (nearest even) in registers
     __device__ __forceinline__ static void rnd(cx<float> c[4]) {
 #pragma unroll
@@ -200,7 +206,10 @@ __global__ void k_bicg_s(const void* r_, const void* v_, void* s_, VecGeo g, con
 
 // Fused end of a BiCGStab iteration, once omega and beta are known:
 //   x += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v) ;
-//   partial ||r||^2 of the stored (rounded) residual
+//   partial ||r||^2 of the stored (rounded) residual.
+// In BF16, x and r are written with streaming stores: the next reads of x
+// (this kernel, next iteration) and r (the s step, after two stencil launches)
+// come after other traffic has evicted them, while p is read at once.
 template <class IO>
 __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, const void* v_, void* r_, VecGeo g,
                            const RhsScal* sc, double2* part) {
@@ -221,9 +230,9 @@ __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, c
             x[c] = x[c] + al * p[c] + om * s[c];
             rn[c] = s[c] - om * t[c];
         }
-        U::st(x_, i, x);
+        if constexpr (IO::planes == 3) U::stnt(x_, i, x); else U::st(x_, i, x);
         U::rnd(rn);  // the stored (rounded) residual feeds p and the norm
-        U::st(r_, i, rn);
+        if constexpr (IO::planes == 3) U::stnt(r_, i, rn); else U::st(r_, i, rn);
 #pragma unroll
         for (int c = 0; c < U::C; c++) {
             p[c] = rn[c] + be * (p[c] - om * v[c]);
