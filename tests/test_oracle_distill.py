@@ -259,3 +259,78 @@ def test_correlator_four_terms_sum_and_shift_invariance():
     C, _, _, _ = oracle.correlator(Lf, Ltf, Lb, Ltb, y0s=[2], vev_mode=0)
     ref = np.mean(Lf[:, 3] * Ltf[:, 2]) - np.mean(Lf[:, 3]) * np.mean(Ltf[:, 2])
     assert abs(C[1] - ref) < 1e-14
+
+
+def _diag_phase_field(dims, spread, seed):
+    """Diagonal SU(3) links diag(e^{i a}, e^{i b}, e^{-i(a+b)}) with Gaussian phases
+    (a U(1) x U(1) embedding): staples, their sums and the projection act entry by
+    entry, so one APE step has a closed form per colour."""
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(seed)
+    ph = spread * rng.standard_normal((V, 4, 2))
+    ph = np.concatenate([ph, -ph.sum(axis=2, keepdims=True)], axis=2)   # [V][mu][c]
+    U = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+    for c in range(3):
+        U[:, :, c, c] = np.exp(1j * ph[:, :, c])
+    return U, ph
+
+
+def _ape_step_diag_closed_form(ph, dims, alpha):
+    """One APE step on a diagonal phase field, written entry by entry with explicit
+    site arithmetic: m_c = (1 - alpha) e^{i phi_k,c(x)} + (alpha/4) sum over the four
+    spatial staples of e^{i (staple phase)}, polar factor m_c/|m_c|, then division by
+    the principal cube root of the determinant.  Returns the new phases [V][mu][c]."""
+    Lx, Ly, Lz, Lt = dims
+    L = (Lx, Ly, Lz, Lt)
+
+    def idx(x):
+        return x[0] + Lx * (x[1] + Ly * (x[2] + Lz * x[3]))
+
+    def step(x, mu, d):
+        y = list(x)
+        y[mu] = (y[mu] + d) % L[mu]
+        return y
+
+    V = int(np.prod(dims))
+    out = ph.copy()
+    for s in range(V):
+        x = [s % Lx, (s // Lx) % Ly, (s // (Lx * Ly)) % Lz, s // (Lx * Ly * Lz)]
+        for k in range(3):
+            w = np.empty(3, dtype=np.complex128)
+            for c in range(3):
+                m = (1 - alpha) * np.exp(1j * ph[s, k, c])
+                for j in range(3):
+                    if j == k:
+                        continue
+                    # forward staple U_j(x) U_k(x+j) U_j(x+k)^+
+                    up = ph[s, j, c] + ph[idx(step(x, j, 1)), k, c] - ph[idx(step(x, k, 1)), j, c]
+                    # backward staple U_j(x-j)^+ U_k(x-j) U_j(x-j+k)
+                    xm = step(x, j, -1)
+                    dn = -ph[idx(xm), j, c] + ph[idx(xm), k, c] + ph[idx(step(xm, k, 1)), j, c]
+                    m += (alpha / 4.0) * (np.exp(1j * up) + np.exp(1j * dn))
+                w[c] = m / abs(m)
+            theta = np.angle(np.prod(w))               # principal argument in (-pi, pi]
+            out[s, k] = np.angle(w) - theta / 3.0
+    return out
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.8])
+def test_ape_closed_form_on_diagonal_phase_links(alpha):
+    """On diagonal (abelian) links with random phases the staple sum is no longer a
+    positive multiple of U, so the result fixes the weighting (1 - alpha) U +
+    (alpha/4) S, the staple paths and the determinant fix; two steps check that a
+    sweep updates every link from the previous sweep."""
+    dims = (4, 4, 4, 2)
+    U, ph = _diag_phase_field(dims, 0.6, 21)
+    S1 = oracle.ape_smear(U, dims, alpha, 1)
+    S2 = oracle.ape_smear(U, dims, alpha, 2)
+    p1 = _ape_step_diag_closed_form(ph, dims, alpha)
+    p2 = _ape_step_diag_closed_form(p1, dims, alpha)
+    for S, p in ((S1, p1), (S2, p2)):
+        ref = np.zeros_like(U)
+        for c in range(3):
+            ref[:, :3, c, c] = np.exp(1j * p[:, :3, c])
+        ref[:, 3] = U[:, 3]
+        assert np.abs(S - ref).max() < 1e-13
+    # the smearing moved the links by far more than the tolerance
+    assert np.abs(S1 - U).max() > 1e-1
