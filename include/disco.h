@@ -66,8 +66,11 @@ enum {
 enum { DISCO_F64 = 0, DISCO_F32 = 1, DISCO_BF16 = 2 };
 /* where a pointer lives */
 enum { DISCO_HOST = 0, DISCO_DEVICE = 1 };
-/* loop channels Gamma */
-enum { DISCO_G_1 = 0, DISCO_G_5 = 1, DISCO_G_X = 2, DISCO_G_Y = 3, DISCO_G_Z = 4 };
+/* loop channels Gamma; a loop code may add DISCO_G_TILDE to ask for the loop of
+ * Gamma~ = gamma_4 Gamma^+ gamma_4, the matrix of the conjugate operator at the
+ * source time of the disconnected correlator (Methodology, the definition under
+ * equation Cdisc): +1, -gamma_5 and -gamma_k for 1, gamma_5 and gamma_k */
+enum { DISCO_G_1 = 0, DISCO_G_5 = 1, DISCO_G_X = 2, DISCO_G_Y = 3, DISCO_G_Z = 4, DISCO_G_TILDE = 8 };
 /* solver methods */
 enum {
     DISCO_CGNR_F64 = 0,    /* conjugate gradients on D^+ D, all FP64 (plain judge) */
@@ -160,6 +163,35 @@ int disco_from_native(disco_ctx* ctx, int prec, int nrhs, const void* in_native,
 int disco_dirac_apply_native(disco_ctx* ctx, const disco_domains* dom, int prec, int dagger, int nrhs,
                              const void* in_native, void* out_native);
 
+/* Even-odd pieces of D (dom = NULL) or D_Lambda, exactly as the production
+ * solver launches them.  The solvers work on the Schur complement of the even
+ * sites, M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe with D = A - kappa H (a
+ * factorisation of D, not in the paper: it leaves D^-1 and so the loop under
+ * equation Cdisc unchanged).  With p = parity (0 even, 1 odd sites, parity of
+ * x+y+z+t):
+ *   out(x) = ca aux(x) + A(x)^-1 [cg aux(x) + cb (H in)(x)]   at every x of parity p,
+ * where H reads `in` at the sites of parity 1-p.  ca = 0, cg = 0, cb = 1 is the
+ * first half of M (A_oo^-1 H_oe); ca = 1, cg = 0, cb = -kappa^2 its second
+ * half; ca = 0, cg = 1, cb = kappa the even-odd source and the odd
+ * reconstruction.  in, aux, aux2 (device, boundary layout complex128
+ * [nrhs][V][4][3]; aux NULL unless ca, cg or a sum with it is asked for, aux2
+ * NULL unless a sum with it is) are read only at the sites of the parity the
+ * piece uses; each is first rounded to prec storage as the solver stores it
+ * (FP32 links and A^-1 for FP32 and BF16).  out (device, same layout) is
+ * written everywhere: the piece at parity p, zero at the other sites.  epi
+ * selects the fused reductions of the launch: 0, DISCO_EPI_DOTAUX,
+ * DISCO_EPI_NORM | DISCO_EPI_DOTIN, or all four; sums (host, [nrhs][4]
+ * complex128, needed when epi != 0) receives per right-hand side
+ * <aux2, out>, ||out||^2, <out, aux>, <aux2, aux> (<a, b> = sum conj(a) b over
+ * the sites of parity p; out before its rounding to storage) at slots 0..3,
+ * zero for the sums not asked for.  One launch of nrhs (1..64, and the plane
+ * limit of disco_dirac_apply_native) right-hand sides: the solver's launch
+ * shape for a block of that width.  EINVAL for odd extents. */
+enum { DISCO_EPI_DOTAUX = 2, DISCO_EPI_NORM = 4, DISCO_EPI_DOTIN = 8, DISCO_EPI_DOTAUXIN = 16 };
+int disco_dirac_eo_apply(disco_ctx* ctx, const disco_domains* dom, int prec, int parity, int nrhs, double ca,
+                         double cg, double cb, int epi, const void* in, const void* aux, const void* aux2, void* out,
+                         double* sums);
+
 /* ---------------------------------------------------------------- options */
 enum {
     DISCO_OPT_GRAPHS = 1, /* 1 (default): inner Krylov iterations run as captured HIP graphs
@@ -180,7 +212,9 @@ int disco_set_option(disco_ctx* ctx, int option, int value);
 typedef struct {
     int method;        /* DISCO_CGNR_F64, DISCO_BICGSTAB_DC, DISCO_FGMRES_NN, DISCO_BICGSTAB_RU */
     double tol;        /* target true ||b - D x|| / ||b|| per right-hand side, FP64 */
-    int max_iter;      /* cap on inner iterations summed over outer cycles */
+    int max_iter;      /* cap on inner iterations summed over outer cycles (0 = 100000);
+                        * BICGSTAB_RU: per wave of rhs_block right-hand sides of the queue,
+                        * and its FP64 fallback runs up to 100000 iterations of its own */
     int inner_prec;    /* DISCO_F32 or DISCO_BF16 (BICGSTAB_DC) */
     double inner_tol;  /* relative reduction asked of each inner solve (e.g. 1e-5) */
     int rhs_block;     /* right-hand sides per batched launch; 0 = the autotuned block for
@@ -205,9 +239,14 @@ typedef struct {
 } disco_solver_stats;
 
 /* Solve D x = b (dom = NULL) or D_Lambda x = b for nrhs right-hand sides b
- * (device, boundary layout complex128).  x (device, same layout) receives the
- * solutions; stats (host, nrhs entries, may be NULL) per right-hand side.
- * Returns DISCO_ENOCONV if any right-hand side misses tol. */
+ * (device, boundary layout complex128): the propagator D^-1 on sources, which
+ * the quark loop under equation Cdisc of the Methodology section traces, and
+ * D_Lambda^-1 of the Domain decomposition subsection.  x (device, same layout)
+ * receives the solutions; stats (host, nrhs entries, may be NULL) per
+ * right-hand side.  Returns DISCO_ENOCONV if any right-hand side misses tol
+ * (every right-hand side is still solved and reported: with BICGSTAB_RU, a
+ * block that stops early hands its lanes in flight to the fallback and runs
+ * the rest of the queue on). */
 int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, const disco_solver_params* p,
                           int nrhs, const void* b, void* x, disco_solver_stats* stats);
 
@@ -247,7 +286,9 @@ int disco_perambulator(disco_ctx* ctx, const void* Vev, int nv, int nsrc, const 
  * equation of the Gaussian-profiled subsection; w = 1 is standard
  * distillation): L[g][t] = sum_i w[t][i] sum_{a,b} Gamma_ab tau[t][i][b][i][a]
  * with tau_tt (device, [T][nv][4][nv][4]) = tau(t,t), w (device [T][nv], or
- * NULL for 1), gammas (host, DISCO_G_* codes), L (device, [ngamma][T]).  This
+ * NULL for 1), gammas (host, DISCO_G_* codes, each optionally with
+ * DISCO_G_TILDE: then Gamma~ = gamma_4 Gamma^+ gamma_4 replaces Gamma), L
+ * (device, [ngamma][T]).  This
  * is the zero-momentum loop sum_x Tr[Gamma D^-1(x,x)] of the Methodology
  * section in its distillation form (no 1/Vs, no sign). */
 int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double* w, const int* gammas, int ngamma,

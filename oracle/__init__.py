@@ -47,8 +47,10 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib_handle = None
 
-# gamma codes shared by name with the library's loop channels
+# gamma codes shared by name with the library's loop channels; G_TILDE added to a
+# code asks for Gamma~ = gamma_0 Gamma^+ gamma_0 (gamma_0 the time gamma)
 G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
+G_TILDE = 8
 
 
 def build(force: bool = False) -> str:
@@ -95,7 +97,10 @@ def gamma(mu: int) -> np.ndarray:
 
 
 def channel_matrix(code: int) -> np.ndarray:
-    """Dirac matrix Gamma of a loop channel: 1, gamma_5, gamma_1, gamma_2, gamma_3."""
+    """Dirac matrix Gamma of a loop channel: 1, gamma_5, gamma_1, gamma_2, gamma_3,
+    or Gamma~ of one of them when the code carries G_TILDE."""
+    if code & G_TILDE:
+        return tilde(channel_matrix(code & ~G_TILDE))
     if code == G_1:
         return np.eye(4, dtype=np.complex128)
     if code == G_5:
@@ -179,6 +184,47 @@ def dense_dirac(U, A, dims, bc, kappa, cut=None, dagger=False) -> np.ndarray:
         M[:, j] = dirac(U, A, dims, bc, kappa, e, cut, dagger).reshape(-1)
         flat[j] = 0
     return M
+
+
+# --------------------------------------------------------------------------
+# even-odd pieces (the Schur factorisation of D on the even sites; a standard
+# technique the paper does not use, checked here because the production solver
+# inverts D through it; D^-1 itself is unchanged)
+# --------------------------------------------------------------------------
+
+def site_parity(dims) -> np.ndarray:
+    """(x + y + z + t) mod 2 for every site s = x + Lx(y + Ly(z + Lz t))."""
+    Lx, Ly, Lz, Lt = dims
+    s = np.arange(Lx * Ly * Lz * Lt)
+    return (s % Lx + (s // Lx) % Ly + (s // (Lx * Ly)) % Lz + s // (Lx * Ly * Lz)) % 2
+
+
+def site_apply(M: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """Site-local 12x12 matrices M [V][12][12] on spinors [..][V][4][3]."""
+    sh = psi.shape
+    flat = psi.reshape(sh[:-2] + (12,))
+    return np.einsum("sij,...sj->...si", M, flat).reshape(sh)
+
+
+def hopping(U, A, dims, bc, kappa, psi, cut=None) -> np.ndarray:
+    """H psi for D = A - kappa H (with D_Lambda's hops when cut is given), from
+    the definition: H = (A - D) / kappa."""
+    return (site_apply(A, psi) - dirac(U, A, dims, bc, kappa, psi, cut)) / kappa
+
+
+def eo_piece(U, A, dims, bc, kappa, parity, ca, cg, cb, psi, aux=None, cut=None, Ainv=None) -> np.ndarray:
+    """out(x) = ca aux(x) + A(x)^-1 [cg aux(x) + cb (H psi_{1-p})(x)] at the sites x
+    of parity p, zero at the others, with psi_{1-p} = psi on the sites of the
+    other parity only.  With the coefficients of the solver these are the
+    pieces of M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, of its source
+    A_ee^-1 (b_e + kappa H_eo A_oo^-1 b_o) and of the odd reconstruction
+    A_oo^-1 (b_o + kappa H_oe x_e).  Ainv: A^-1 per site when already at hand."""
+    par = site_parity(dims)
+    pin = np.where((par == 1 - parity)[:, None, None], psi, 0)
+    h = hopping(U, A, dims, bc, kappa, pin, cut)
+    a = np.zeros_like(psi) if aux is None else aux
+    out = ca * a + site_apply(np.linalg.inv(A) if Ainv is None else Ainv, cg * a + cb * h)
+    return np.where((par == parity)[..., :, None, None], out, 0)
 
 
 # --------------------------------------------------------------------------

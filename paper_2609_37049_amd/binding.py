@@ -19,6 +19,8 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -
 F64, F32, BF16 = 0, 1, 2
 HOST, DEVICE = 0, 1
 G_1, G_5, G_X, G_Y, G_Z = 0, 1, 2, 3, 4
+G_TILDE = 8  # added to a loop code: the loop of gamma_4 Gamma^+ gamma_4
+EPI_DOTAUX, EPI_NORM, EPI_DOTIN, EPI_DOTAUXIN = 2, 4, 8, 16
 CGNR_F64, BICGSTAB_DC, FGMRES_NN, BICGSTAB_RU = 0, 1, 2, 3
 K_STENCIL = 0
 K_NN = 2
@@ -76,6 +78,7 @@ _SIGS = {
     "disco_to_native": ([P, I, I, P, P], I),
     "disco_from_native": ([P, I, I, P, P], I),
     "disco_dirac_apply_native": ([P, P, I, I, I, P, P], I),
+    "disco_dirac_eo_apply": ([P, P, I, I, I, D, D, D, I, P, P, P, P, P], I),
     "disco_solve_multi_rhs": ([P, P, ctypes.POINTER(SolverParams), I, P, P, ctypes.POINTER(SolverStats)], I),
     "disco_profile_enable": ([P, I], I),
     "disco_profile_reset": ([P], I),
@@ -343,6 +346,20 @@ class Context:
     def dirac_apply_native(self, dom, prec, nat_in, nat_out, n, dagger=False):
         self._chk(lib().disco_dirac_apply_native(self.h, None if dom is None else dom.h, prec, int(dagger), n,
                                                  _dptr(nat_in), _dptr(nat_out)))
+
+    def dirac_eo_apply(self, psi, parity, ca, cg, cb, prec=F64, dom: Domains | None = None, aux=None, aux2=None,
+                       epi=0):
+        """The even-odd piece out = ca aux + A^-1 (cg aux + cb H psi) at the sites of
+        `parity` (zero elsewhere), as the solver launches it; returns (out, sums)
+        with sums [n][4] complex (None when epi = 0)."""
+        n = psi.shape[0]
+        out = self.empty_spinors(n)
+        sums = np.zeros((n, 4), dtype=np.complex128) if epi else None
+        self._chk(lib().disco_dirac_eo_apply(self.h, None if dom is None else dom.h, prec, int(parity), n,
+                                             float(ca), float(cg), float(cb), int(epi), _dptr(psi), _dptr(aux),
+                                             _dptr(aux2), _dptr(out),
+                                             None if sums is None else sums.ctypes.data_as(P)))
+        return out, sums
 
     # -- solver
     @staticmethod

@@ -451,6 +451,24 @@ __device__ __forceinline__ cd channel_entry(int g, int a, int b) {
     return gamma_entry(g - DISCO_G_X, a, b);
 }
 
+// Entry of the matrix a loop code asks for: Gamma, or with DISCO_G_TILDE
+// Gamma~ = gamma_4 Gamma^+ gamma_4, formed as that product.
+__device__ __forceinline__ cd loop_entry(int code, int a, int b) {
+    const int g = code & ~DISCO_G_TILDE;
+    if (!(code & DISCO_G_TILDE)) return channel_entry(g, a, b);
+    cd acc = mk(0.0, 0.0);
+    for (int c = 0; c < 4; c++) {
+        const cd l = gamma_entry(3, a, c);
+        if (l.re == 0 && l.im == 0) continue;
+        for (int d = 0; d < 4; d++) {
+            const cd r = gamma_entry(3, d, b);
+            if (r.re == 0 && r.im == 0) continue;
+            acc = acc + l * cj(channel_entry(g, d, c)) * r;
+        }
+    }
+    return acc;
+}
+
 // L[g][t] = sum_i w[t][i] sum_{a,b} Gamma_ab tau[t][i][b][i][a]
 __global__ void k_loops(const double2* __restrict__ tau, int T, int nv, const double* __restrict__ w,
                         const int* __restrict__ gam, int ng, double2* __restrict__ L) {
@@ -461,7 +479,7 @@ __global__ void k_loops(const double2* __restrict__ tau, int T, int nv, const do
         cd s = mk(0.0, 0.0);
         for (int a = 0; a < 4; a++)
             for (int b = 0; b < 4; b++) {
-                cd G = channel_entry(gam[g], a, b);
+                cd G = loop_entry(gam[g], a, b);
                 if (G.re == 0 && G.im == 0) continue;
                 double2 v = tau[((((long)t * nv + i) * 4 + b) * nv + i) * 4 + a];
                 s = s + G * mk(v.x, v.y);
@@ -880,7 +898,9 @@ int disco_loops(disco_ctx* ctx, const void* tau_tt, int T, int nv, const double*
     if (!ctx) return DISCO_EINVAL;
     return guarded(ctx, [&] {
         REQUIRE(tau_tt && gammas && L && T > 0 && nv > 0 && ngamma > 0, DISCO_EINVAL, "bad argument");
-        for (int g = 0; g < ngamma; g++) REQUIRE(gammas[g] >= 0 && gammas[g] <= 4, DISCO_EINVAL, "bad channel");
+        for (int g = 0; g < ngamma; g++)
+            REQUIRE((gammas[g] & ~DISCO_G_TILDE) >= 0 && (gammas[g] & ~DISCO_G_TILDE) <= 4, DISCO_EINVAL,
+                    "bad channel %d", gammas[g]);
         activate(ctx);
         int* gd = (int*)ws_get(ctx, "lp_g", sizeof(int) * ngamma);
         HIPCHK(hipMemcpyAsync(gd, gammas, sizeof(int) * ngamma, hipMemcpyHostToDevice, ctx->stream));

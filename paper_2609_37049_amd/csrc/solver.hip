@@ -47,6 +47,8 @@ struct RhsScal {
 // inner iterations without a halving of a lane's inner residual before it
 // stops (its Krylov process then restarts)
 constexpr int kRuStall = 100;
+// iterations the FP64 CGNR fallback of the reliable-update solver may take
+constexpr int kFallbackIters = 100000;
 // threads of a per-RHS scalar step (one block per right-hand side folds its
 // partial sums; more threads keep more loads in flight)
 constexpr int kScalarBlock = 1024;
@@ -403,6 +405,15 @@ __global__ void k_lane_restart(double2* __restrict__ x64, double2* __restrict__ 
         const long j = row * n + lanes[i - row * m];
         x64[j] = make_double2(0.0, 0.0);
         r64[j] = b64[j];
+    }
+}
+
+// b = 0 in lanes[0..m) (idle lanes of a block whose queue has run dry)
+__global__ void k_lane_clear(double2* __restrict__ b64, long V, int n, const int* __restrict__ lanes, int m) {
+    const long tot = 12 * V * m;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long row = i / m;
+        b64[row * n + lanes[i - row * m]] = make_double2(0.0, 0.0);
     }
 }
 
@@ -1118,12 +1129,16 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
 // residual and the scalars carry on.  Lanes that break down, or whose true
 // residual does not follow the recursive one, restart their Krylov process.
 // The inner vectors keep the scale 1/||b|| of the start.
-template <class IO>
 //
 // With a feeder (continuous batching), a lane whose right-hand side has
 // converged hands its solution over at that update and takes the next one
 // from the queue, with a Krylov process of its own; st then has one entry per
-// right-hand side of the queue.
+// right-hand side of the queue.  When the block stops early (the worst true
+// residual stalls, or the iteration cap of the lanes in flight is reached),
+// the lanes in flight get the FP64 fallback (when allowed) and are handed
+// over, and the rest of the queue runs on in a fresh Krylov process: one hard
+// right-hand side does not cost the ones behind it.
+template <class IO>
 static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b64, double2* x64,
                      const uint8_t* mask, disco_solver_stats* st, disco::LaneFeeder* feed = nullptr,
                      long long* block_iters = nullptr) {
@@ -1137,24 +1152,6 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     void* efull = ws_get(ctx, "dc_e", nbp);
     const VecGeo g64 = vgeo(V, DISCO_F64, n);
     const double tol2 = P.tol * P.tol;
-    // queue state: lane -> right-hand side (-1 idle), and where each started
-    std::vector<int> lane_src(n, -1), lane_it0(n, 0), lane_up0(n, 0);
-    int next = 0;
-    if (feed) {
-        for (int r = 0; r < n; r++) {
-            if (next >= feed->total) break;
-            feed->load(r, next, n);
-            lane_src[r] = next++;
-        }
-    }
-    k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
-    norm2<IO64>(w, b64, g64);
-    k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
-    copy_scale<IO64, IO64>(w, b64, r64, 0);
-    // with a queue the cap applies per wave of right-hand sides
-    const int waves = feed ? std::max(1, (feed->total + n - 1) / n) : 1;
-    const int max_iter =
-        (int)std::min<long long>(2000000000LL, (long long)(P.max_iter > 0 ? P.max_iter : 100000) * waves);
     const int check = P.check_every > 0 ? P.check_every : 2;
     const double delta = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-3);
     const bool eo = ctx->opt_eo && disco::eo_supported(ctx);
@@ -1169,6 +1166,13 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     void* ee = eo ? ws_get(ctx, "eo_ee", hb) : efull;
     void* eodd = eo ? ws_get(ctx, "eo_eo", hb) : nullptr;
     const void* Ai = prec == DISCO_F64 ? (const void*)ctx->Ai64 : (const void*)ctx->Ai32;
+    const bool trace = getenv("DISCO_TRACE") != nullptr;
+    // queue state: lane -> right-hand side (-1 idle), and where each started
+    std::vector<int> lane_src(n, -1), lane_it0(n, 0), lane_up0(n, 0);
+    int next = 0;
+    int* dflag = feed ? (int*)ws_get(ctx, "ru_flag", sizeof(int) * n) : nullptr;
+    int* dlane = feed ? (int*)ws_get(ctx, "ru_lane", sizeof(int) * n) : nullptr;
+    std::vector<int> hflag(n, 0), hlane(n, 0);
     // scale[r] r64 -> rhat, the inner system's source (in even-odd form the
     // scaled residual is split into re, ro on the way, without a full-lattice copy)
     auto prepare = [&]() {
@@ -1203,135 +1207,176 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     op.eo = eo;
     op.Vv = Vv;
     op.nsb = disco::stencil_nsb(ctx, n, eo);
-    prepare();
-    int outer = 0, stall = 0, it_best = 0;
-    double last_worst = 1e300;
-    const bool trace = getenv("DISCO_TRACE") != nullptr;
-    std::vector<int> done_at(w.n, 0);
-    int* dflag = feed ? (int*)ws_get(ctx, "ru_flag", sizeof(int) * n) : nullptr;
-    int* dlane = feed ? (int*)ws_get(ctx, "ru_lane", sizeof(int) * n) : nullptr;
-    std::vector<int> hflag(n, 0), hlane(n, 0);
-    // hand over the lanes whose right-hand side is finished (all lanes still
-    // holding one when final), with their statistics
-    auto hand_over = [&](int it, bool final, int fb) {
-        std::vector<int> lanes, js;
-        for (int r = 0; r < n; r++) {
-            if (lane_src[r] < 0 || (!final && !w.h[r].outer_done)) continue;
-            const int j = lane_src[r];
-            disco_solver_stats& q = st[j];
-            q.iters = it - lane_it0[r];
-            q.outer_iters = std::max(1, outer - lane_up0[r]);
-            q.fallback_used = fb;
-            q.true_rel_residual = w.h[r].bb > 0 ? std::sqrt(w.h[r].rr / w.h[r].bb) : 0.0;
-            q.converged = q.true_rel_residual <= P.tol;
-            lanes.push_back(r);
-            js.push_back(j);
-            lane_src[r] = -1;
-        }
-        if (!lanes.empty()) feed->store(lanes, js, n);
-        return lanes;
-    };
-    std::function<bool(int)> refresh = [&](int it) -> bool {
-        fold_in();
-        outer++;
-        // finished lanes hand over and take the next right-hand sides; again
-        // while a new one is finished at once (a zero right-hand side)
-        for (bool again = feed != nullptr; again;) {
-            again = false;
-            const std::vector<int> freed = hand_over(it, false, 0);
-            bool refill = false;
-            std::fill(hflag.begin(), hflag.end(), 0);
-            for (int r : freed) {
-                if (next >= feed->total) continue;
-                feed->load(r, next, n);
-                lane_src[r] = next++;
-                lane_it0[r] = it;
-                lane_up0[r] = outer;
-                hflag[r] = 1;
-                refill = true;
+    long long iters_all = 0;
+    // one episode per Krylov process of the block (a single one unless the
+    // block stops before the queue is empty)
+    for (;;) {
+        int outer = 0, stall = 0, it_best = 0;
+        double last_worst = 1e300;
+        bool gave_up = false;
+        int held = 0;
+        if (feed) {
+            // fill every lane from the queue; lanes left idle get b = 0 (they
+            // may still hold a right-hand side of the previous episode), which
+            // marks them finished at the start
+            int m = 0;
+            for (int r = 0; r < n; r++) {
+                lane_it0[r] = 0;
+                lane_up0[r] = 0;
+                if (next < feed->total) {
+                    feed->load(r, next, n);
+                    lane_src[r] = next++;
+                    held++;
+                } else {
+                    lane_src[r] = -1;
+                    hlane[m++] = r;
+                }
             }
-            if (refill) {
-                int m = 0;
-                for (int r = 0; r < n; r++)
-                    if (hflag[r]) hlane[m++] = r;
-                HIPCHK(hipMemcpyAsync(dflag, hflag.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+            if (m) {
                 HIPCHK(hipMemcpyAsync(dlane, hlane.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
-                hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n, dlane, m);
-                norm2<IO64>(w, b64, g64);
-                k_sc_lane_start<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
-                pull(w);
-                // a new right-hand side starts the progress measure afresh
-                last_worst = 1e300;
-                stall = 0;
-                for (int r = 0; r < n; r++) again |= hflag[r] && w.h[r].outer_done;
+                hipLaunchKernelGGL(k_lane_clear, dim3(1024), dim3(256), 0, ctx->stream, b64, V, n, dlane, m);
             }
         }
-        bool open = false;
-        double worst = 0;
-        for (auto& s : w.h) {
-            open |= !s.outer_done;
-            if (s.bb > 0 && !s.outer_done) worst = std::max(worst, std::sqrt(s.rr / s.bb));
-        }
-        if (trace) {
-            fprintf(stderr, "[disco] reliable update %d at iteration %d: worst true rel residual %.3e\n", outer, it,
-                    worst);
-            for (int i = 0; i < w.n; i++)
-                if (w.h[i].outer_done && !done_at[i]) fprintf(stderr, "[disco] lane %d done at iteration %d\n", i, it);
-        }
-        for (int i = 0; i < w.n; i++)
-            if (w.h[i].outer_done && !done_at[i]) done_at[i] = it;
-        if (!open) return false;
-        if (worst > 0.5 * last_worst) {
-            stall++;
-        } else {
-            stall = 0;
-            it_best = it;
-        }
-        last_worst = std::min(last_worst, worst);
-        // no halving of the worst true residual over 8 updates and 800
-        // iterations (lanes restart on their own after 100): leave it to the fallback
-        if (stall >= 8 && it - it_best >= 800) return false;
+        k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+        norm2<IO64>(w, b64, g64);
+        k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+        copy_scale<IO64, IO64>(w, b64, r64, 0);
+        // with a queue the cap applies per wave of the right-hand sides this
+        // episode starts with or still has to take
+        const int waves = feed ? std::max(1, (held + (feed->total - next) + n - 1) / n) : 1;
+        const int max_iter =
+            (int)std::min<long long>(2000000000LL, (long long)(P.max_iter > 0 ? P.max_iter : 100000) * waves);
         prepare();
-        const VecGeo gh = vgeo(Vv, prec, n);
-        void* r = ws_get(ctx, "bi_r", nbp);
-        void* rh = ws_get(ctx, "bi_rh", nbp);
-        void* p = ws_get(ctx, "bi_p", nbp);
-        hipLaunchKernelGGL(k_ru_refresh<IO>, dim3(gh.nb), dim3(gh.bd), 0, ctx->stream, r, rhat, p, rh, ee, gh, w.sc,
-                           w.part);
-        k_sc_ru_refresh<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
-        HIPCHK(hipGetLastError());
-        return true;
-    };
-    // a marked lane iterates on until the update, but no further than delta^2
-    const int iters =
-        bicg_run<IO>(w, op, prec, rhat, ee, mask, delta, max_iter, check, 0, &refresh, kRuStall, delta * delta * delta * delta);
-    pull(w);
-    bool done = true;
-    for (auto& s : w.h) done &= s.outer_done != 0;
-    if (!done) {
-        fold_in();  // the correction since the last update (zero right after one)
-        done = true;
+        std::vector<int> done_at(w.n, 0);
+        // hand over the lanes whose right-hand side is finished (all lanes still
+        // holding one when final), with their statistics
+        auto hand_over = [&](int it, bool final, int fb) {
+            std::vector<int> lanes, js;
+            for (int r = 0; r < n; r++) {
+                if (lane_src[r] < 0 || (!final && !w.h[r].outer_done)) continue;
+                const int j = lane_src[r];
+                disco_solver_stats& q = st[j];
+                q.iters = it - lane_it0[r];
+                q.outer_iters = std::max(1, outer - lane_up0[r]);
+                q.fallback_used = fb;
+                q.true_rel_residual = w.h[r].bb > 0 ? std::sqrt(w.h[r].rr / w.h[r].bb) : 0.0;
+                q.converged = q.true_rel_residual <= P.tol;
+                lanes.push_back(r);
+                js.push_back(j);
+                lane_src[r] = -1;
+            }
+            if (!lanes.empty()) feed->store(lanes, js, n);
+            return lanes;
+        };
+        std::function<bool(int)> refresh = [&](int it) -> bool {
+            fold_in();
+            outer++;
+            // finished lanes hand over and take the next right-hand sides; again
+            // while a new one is finished at once (a zero right-hand side)
+            for (bool again = feed != nullptr; again;) {
+                again = false;
+                const std::vector<int> freed = hand_over(it, false, 0);
+                bool refill = false;
+                std::fill(hflag.begin(), hflag.end(), 0);
+                for (int r : freed) {
+                    if (next >= feed->total) continue;
+                    feed->load(r, next, n);
+                    lane_src[r] = next++;
+                    lane_it0[r] = it;
+                    lane_up0[r] = outer;
+                    hflag[r] = 1;
+                    refill = true;
+                }
+                if (refill) {
+                    int m = 0;
+                    for (int r = 0; r < n; r++)
+                        if (hflag[r]) hlane[m++] = r;
+                    HIPCHK(hipMemcpyAsync(dflag, hflag.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+                    HIPCHK(hipMemcpyAsync(dlane, hlane.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+                    hipLaunchKernelGGL(k_lane_restart, dim3(1024), dim3(256), 0, ctx->stream, x64, r64, b64, V, n,
+                                       dlane, m);
+                    norm2<IO64>(w, b64, g64);
+                    k_sc_lane_start<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, dflag, tol2);
+                    pull(w);
+                    // a new right-hand side starts the progress measure afresh
+                    last_worst = 1e300;
+                    stall = 0;
+                    for (int r = 0; r < n; r++) again |= hflag[r] && w.h[r].outer_done;
+                }
+            }
+            bool open = false;
+            double worst = 0;
+            for (auto& s : w.h) {
+                open |= !s.outer_done;
+                if (s.bb > 0 && !s.outer_done) worst = std::max(worst, std::sqrt(s.rr / s.bb));
+            }
+            if (trace) {
+                fprintf(stderr, "[disco] reliable update %d at iteration %d: worst true rel residual %.3e\n", outer, it,
+                        worst);
+                for (int i = 0; i < w.n; i++)
+                    if (w.h[i].outer_done && !done_at[i])
+                        fprintf(stderr, "[disco] lane %d done at iteration %d\n", i, it);
+            }
+            for (int i = 0; i < w.n; i++)
+                if (w.h[i].outer_done && !done_at[i]) done_at[i] = it;
+            if (!open) return false;
+            if (worst > 0.5 * last_worst) {
+                stall++;
+            } else {
+                stall = 0;
+                it_best = it;
+            }
+            last_worst = std::min(last_worst, worst);
+            // no halving of the worst true residual over 8 updates and 800
+            // iterations (lanes restart on their own after 100): leave it to
+            // the fallback.  The correction is already folded in, and the
+            // inner state is not refreshed, so nothing is pending.
+            if (stall >= 8 && it - it_best >= 800) {
+                gave_up = true;
+                return false;
+            }
+            prepare();
+            const VecGeo gh = vgeo(Vv, prec, n);
+            void* r = ws_get(ctx, "bi_r", nbp);
+            void* rh = ws_get(ctx, "bi_rh", nbp);
+            void* p = ws_get(ctx, "bi_p", nbp);
+            hipLaunchKernelGGL(k_ru_refresh<IO>, dim3(gh.nb), dim3(gh.bd), 0, ctx->stream, r, rhat, p, rh, ee, gh,
+                               w.sc, w.part);
+            k_sc_ru_refresh<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
+            HIPCHK(hipGetLastError());
+            return true;
+        };
+        // a marked lane iterates on until the update, but no further than delta^2
+        const int iters = bicg_run<IO>(w, op, prec, rhat, ee, mask, delta, max_iter, check, 0, &refresh, kRuStall,
+                                       delta * delta * delta * delta);
+        pull(w);
+        bool done = true;
         for (auto& s : w.h) done &= s.outer_done != 0;
-    }
-    int fb = 0;
-    int total = iters;
-    if (!done && P.fallback) {
-        fb = 1;
-        const int cap = P.max_iter > 0 ? P.max_iter : 100000;
-        cgnr_correct(w, b64, x64, r64, mask, P.tol, std::max(1, feed ? cap : max_iter - iters), check, &total);
-    }
-    if (block_iters) *block_iters = total;
-    if (feed) {
-        hand_over(total, true, fb);
-        // right-hand sides the queue never reached (the solve gave up first)
-        if (next < feed->total) k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
-        for (int j = next; j < feed->total; j++) {
-            st[j] = disco_solver_stats{0, 0, fb, 0, 1.0};
-            feed->store(std::vector<int>{0}, std::vector<int>{j}, n);  // x = 0
+        if (!done && !gave_up) {
+            fold_in();  // the correction since the last update (zero right after one)
+            done = true;
+            for (auto& s : w.h) done &= s.outer_done != 0;
         }
-        return;
+        int fb = 0;
+        int total = iters;
+        if (!done && P.fallback) {
+            // the FP64 judge has a budget of its own: max_iter caps the inner iterations
+            fb = 1;
+            cgnr_correct(w, b64, x64, r64, mask, P.tol, kFallbackIters, check, &total);
+        }
+        iters_all += total;
+        if (feed) {
+            hand_over(total, true, fb);
+            if (trace && next < feed->total)
+                fprintf(stderr, "[disco] block stopped early; %d right-hand sides left start a new process\n",
+                        feed->total - next);
+            if (next < feed->total) continue;
+            break;
+        }
+        fill_stats(w, P, total, std::max(1, outer), fb, st);
+        break;
     }
-    fill_stats(w, P, total, std::max(1, outer), fb, st);
+    if (block_iters) *block_iters = iters_all;
 }
 
 // --------------------------------------------------------------- FGMRES
@@ -1811,4 +1856,99 @@ extern "C" int disco_solve_multi_rhs(disco_ctx* ctx, const disco_domains* dom, c
         return DISCO_ENOCONV;
     }
     return rc;
+}
+
+// ----------------------------------------------------------------- even-odd pieces at the boundary
+namespace {
+// the NQ fused sums of right-hand side blockIdx.x into out[r][4] at slots s0..s3
+template <int NQ>
+__global__ void k_fold_epi(const double2* part, int nparts, int s0, int s1, int s2, int s3, double2* out) {
+    cd q[NQ];
+    fold<NQ>(part, blockIdx.x, nparts, q);
+    if (threadIdx.x) return;
+    const int slot[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int k = 0; k < NQ; k++) out[(long)blockIdx.x * 4 + slot[k]] = make_double2(q[k].re, q[k].im);
+}
+
+template <class IO>
+void eo_boundary(disco_ctx* ctx, const disco_domains* dom, int prec, int p, int n, double ca, double cg, double cb,
+                 int epi, const void* in, const void* aux, const void* aux2, void* out, double* sums) {
+    const long V = ctx->V;
+    const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2];
+    const size_t full = disco::native_bytes(ctx, prec, n), half = full / 2;
+    void* tmp = ws_get(ctx, "eoa_full", full);
+    void* hin[2] = {ws_get(ctx, "eoa_in0", half), ws_get(ctx, "eoa_in1", half)};
+    void* haux[2] = {ws_get(ctx, "eoa_aux0", half), ws_get(ctx, "eoa_aux1", half)};
+    void* haux2[2] = {ws_get(ctx, "eoa_aux20", half), ws_get(ctx, "eoa_aux21", half)};
+    void* hout = ws_get(ctx, "eoa_out", half);
+    void* hzero = ws_get(ctx, "eoa_zero", half);
+    const int grid = site_grid(V, n);
+    auto split = [&](const void* src, void* h[2]) {
+        disco::to_native(ctx, prec, n, src, tmp);
+        hipLaunchKernelGGL(k_eo_split<IO>, dim3(grid), dim3(256), 0, ctx->stream, tmp, h[0], h[1], V, n, Lx, Ly, Lz);
+    };
+    split(in, hin);
+    if (aux) split(aux, haux);
+    if (aux2) split(aux2, haux2);
+    const int nq = disco::nq_of(epi);
+    const int nsb = disco::stencil_nsb(ctx, n, true);
+    double2* part = nq ? (double2*)ws_get(ctx, "eoa_part", sizeof(double2) * (size_t)nsb * nq * n) : nullptr;
+    disco::StencilCall c{prec, 0, n, hin[1 - p], hout, aux ? haux[p] : nullptr, aux2 ? haux2[p] : nullptr,
+                         dom ? dom->d_mask : nullptr, part, epi, p, ca, cg, cb};
+    disco::stencil_launch(ctx, c);
+    const VecGeo gh = vgeo(V / 2, prec, n);
+    k_zero<IO><<<1024, 256, 0, ctx->stream>>>(hzero, gh.total);
+    hipLaunchKernelGGL(k_eo_merge<IO>, dim3(grid), dim3(256), 0, ctx->stream, p == 0 ? hout : hzero,
+                       p == 1 ? hout : hzero, tmp, V, n, Lx, Ly, Lz);
+    disco::from_native(ctx, prec, n, tmp, out);
+    if (nq) {
+        double2* d = (double2*)ws_get(ctx, "eoa_sums", sizeof(double2) * 4 * n);
+        HIPCHK(hipMemsetAsync(d, 0, sizeof(double2) * 4 * n, ctx->stream));
+        int slot[4] = {0, 0, 0, 0}, k = 0;
+        const int bits[4] = {disco::EPI_DOTAUX, disco::EPI_NORM, disco::EPI_DOTIN, disco::EPI_DOTAUXIN};
+        for (int b = 0; b < 4; b++)
+            if (epi & bits[b]) slot[k++] = b;
+        if (nq == 1) k_fold_epi<1><<<n, kScalarBlock, 0, ctx->stream>>>(part, nsb, slot[0], 0, 0, 0, d);
+        else if (nq == 2) k_fold_epi<2><<<n, kScalarBlock, 0, ctx->stream>>>(part, nsb, slot[0], slot[1], 0, 0, d);
+        else k_fold_epi<4><<<n, kScalarBlock, 0, ctx->stream>>>(part, nsb, slot[0], slot[1], slot[2], slot[3], d);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(sums, d, sizeof(double2) * 4 * n, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+}  // namespace
+
+extern "C" int disco_dirac_eo_apply(disco_ctx* ctx, const disco_domains* dom, int prec, int parity, int nrhs,
+                                    double ca, double cg, double cb, int epi, const void* in, const void* aux,
+                                    const void* aux2, void* out, double* sums) {
+    if (!ctx) return DISCO_EINVAL;
+    return guarded(ctx, [&] {
+        using namespace disco;
+        REQUIRE(in && out, DISCO_EINVAL, "NULL spinor");
+        REQUIRE(prec >= 0 && prec <= 2, DISCO_EINVAL, "bad precision %d", prec);
+        REQUIRE(parity == 0 || parity == 1, DISCO_EINVAL, "parity is 0 or 1");
+        REQUIRE(!dom || dom->ctx == ctx, DISCO_EINVAL, "domains belong to another context");
+        REQUIRE(ctx->have_clover, DISCO_ESTATE, "operator applied before clover_setup");
+        REQUIRE(eo_supported(ctx), DISCO_EINVAL, "even-odd pieces need even extents");
+        REQUIRE(nrhs >= 1 && nrhs <= max_rhs_block(ctx), DISCO_EINVAL, "nrhs must be in 1..%d", max_rhs_block(ctx));
+        const int all4 = EPI_DOTAUX | EPI_NORM | EPI_DOTIN | EPI_DOTAUXIN;
+        REQUIRE(epi == 0 || epi == EPI_DOTAUX || epi == (EPI_NORM | EPI_DOTIN) || epi == all4, DISCO_EINVAL,
+                "epilogue %d is not one the solver launches", epi);
+        const bool need_aux = ca != 0.0 || cg != 0.0 || (epi & (EPI_DOTIN | EPI_DOTAUXIN));
+        REQUIRE(!need_aux || aux, DISCO_EINVAL, "aux is needed for ca, cg or the sums with it");
+        REQUIRE(!(epi & (EPI_DOTAUX | EPI_DOTAUXIN)) || aux2, DISCO_EINVAL, "aux2 is needed for its sums");
+        REQUIRE(!epi || sums, DISCO_EINVAL, "sums is NULL");
+        REQUIRE(out != in && out != aux && out != aux2, DISCO_EINVAL, "out must not alias an input");
+        activate(ctx);
+        const void* a1 = need_aux ? aux : nullptr;
+        const void* a2 = (epi & (EPI_DOTAUX | EPI_DOTAUXIN)) ? aux2 : nullptr;
+        if (prec == DISCO_F64)
+            eo_boundary<IO64>(ctx, dom, prec, parity, nrhs, ca, cg, cb, epi, in, a1, a2, out, sums);
+        else if (prec == DISCO_F32)
+            eo_boundary<IO32>(ctx, dom, prec, parity, nrhs, ca, cg, cb, epi, in, a1, a2, out, sums);
+        else
+            eo_boundary<IOBF>(ctx, dom, prec, parity, nrhs, ca, cg, cb, epi, in, a1, a2, out, sums);
+    });
 }

@@ -104,6 +104,27 @@ def random_spinor(V: int, n: int, seed: int) -> np.ndarray:
     return re + 1j * im
 
 
+def random_colour_vectors(T: int, nv: int, Vs: int, seed: int) -> np.ndarray:
+    """Seeded stand-ins for smearing vectors: nv complex Gaussian colour fields
+    per timeslice, each of unit norm, complex128 [T][nv][Vs][3] (the layout of
+    the eigenvectors).  V^+ D^-1 V is defined for any V, so solver and
+    projection checks can use these in place of Laplacian eigenvectors."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal((T, nv, Vs, 3)) + 1j * rng.standard_normal((T, nv, Vs, 3))
+    return v / np.sqrt((np.abs(v) ** 2).sum(axis=(2, 3), keepdims=True))
+
+
+def random_spinor_device(V: int, n: int, seed: int, device="cuda:0"):
+    """n Gaussian spinor fields, N(0,1) per real component, drawn on the GPU by
+    torch's seeded generator (for multi-gigabyte blocks that need not pass
+    through host memory): complex128 torch tensor [n][V][4][3]."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    re = torch.randn((n, V, 4, 3), generator=g, device=device, dtype=torch.float64)
+    im = torch.randn((n, V, 4, 3), generator=g, device=device, dtype=torch.float64)
+    return torch.complex(re, im)
+
+
 def tiling_cuts(dims, block) -> np.ndarray:
     """Cut masks for a regular tiling with block extent block[mu] along mu
     (block[mu] == dims[mu] means no cut in that direction).  Returns uint8

@@ -14,6 +14,8 @@ from lattice_fixtures import unit_field, coords, momenta
 pytestmark = pytest.mark.gpu
 BC = (1, 1, 1, -1)
 CODES = [0, 1, 2, 3, 4]
+TCODES = [c | 8 for c in CODES]   # the loops of Gamma~ = gamma_4 Gamma^+ gamma_4
+NC = len(CODES)
 
 
 def _say(*a):
@@ -112,6 +114,26 @@ def test_loops_parity(disco):
         assert _rel(L, ref) < 1e-14
 
 
+def test_tilde_loops_parity(disco):
+    """Loop codes with the tilde flag give the loops of gamma_4 Gamma^+ gamma_4,
+    formed in the library's loop kernel (the oracle forms the matrix product)."""
+    rng = np.random.default_rng(18)
+    T, nv = 6, 5
+    tau = rng.standard_normal((T, nv, 4, nv, 4)) + 1j * rng.standard_normal((T, nv, 4, nv, 4))
+    w = rng.random((T, nv))
+    ctx = disco.Context((2, 2, 2, T), BC)
+    for ww in (None, w):
+        L = ctx.loops(ctx.dev(tau), CODES + TCODES, None if ww is None else ctx.dev(ww)).cpu().numpy()
+        ref = oracle.loops(tau, CODES + TCODES, ww)
+        assert _rel(L, ref) < 1e-14
+        # +L for 1, -L for gamma_5 and gamma_k (a consequence, checked on the GPU's output)
+        for g in range(NC):
+            s = 1.0 if CODES[g] == 0 else -1.0
+            assert np.abs(L[NC + g] - s * L[g]).max() <= 1e-14 * np.abs(L[g]).max()
+    with pytest.raises(disco.DiscoError):
+        ctx.loops(ctx.dev(tau), [16])
+
+
 @pytest.mark.parametrize("vev_mode", [0, 1])
 def test_correlator_parity(disco, vev_mode):
     rng = np.random.default_rng(9)
@@ -128,10 +150,6 @@ def test_correlator_parity(disco, vev_mode):
             assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(rC).max())
 
 
-def _tilde_sign(code):
-    return 1.0 if code == 0 else -1.0
-
-
 @pytest.fixture(scope="module")
 def plain_oracle():
     """Oracle loops for the plain FP64 workload (4^4, Nv=4, 2^4 domains)."""
@@ -145,7 +163,8 @@ def plain_oracle():
     T = dims[3]
     tau_f = np.stack([oracle.perambulator_tt(U, A, dims, BC, pre.kappa, Vo, t) for t in range(T)])
     tau_b = np.stack([oracle.perambulator_tt(U, A, dims, BC, pre.kappa, Vo, t, cut=cut) for t in range(T)])
-    return pre, U, A, Vo, cut, oracle.loops(tau_f, CODES), oracle.loops(tau_b, CODES), tau_f, tau_b
+    return (pre, U, A, Vo, cut, oracle.loops(tau_f, CODES + TCODES), oracle.loops(tau_b, CODES + TCODES), tau_f,
+            tau_b)
 
 
 @pytest.mark.parametrize("method,blk", [("CGNR_F64", 8), ("BICGSTAB_DC", 8), ("BICGSTAB_RU", 8), ("BICGSTAB_RU", 5)])
@@ -164,21 +183,21 @@ def test_end_to_end_plain_workload(disco, plain_oracle, method, blk):
     Vg, _ = ctx.laplace_eigvecs(pre.nv, 1e-13)
     dom = ctx.domains(cut)
     P = ctx.params(method=getattr(disco, method), tol=1e-12, inner_prec=disco.F32, rhs_block=blk)
-    Lf, tf, st = ctx.loops_distill(Vg, CODES, P, None, want_tau=True)
-    Lb, tb, stb = ctx.loops_distill(Vg, CODES, P, dom, want_tau=True)
+    Lf, tf, st = ctx.loops_distill(Vg, CODES + TCODES, P, None, want_tau=True)
+    Lb, tb, stb = ctx.loops_distill(Vg, CODES + TCODES, P, dom, want_tau=True)
     # packing: 2 temporal layers -> half as many block solves as logical sources
     assert ctx.last_solves() == 4 * pre.nv * dims[3] // 2
     Lf, Lb = Lf.cpu().numpy(), Lb.cpu().numpy()
-    for g in range(len(CODES)):
+    for g in range(2 * NC):
         for La, Lr in ((Lf[g], Lf_o[g]), (Lb[g], Lb_o[g])):
             err = np.abs(La - Lr).max() / max(np.abs(Lr).max(), 1e-300)
             assert err < 1e-10, (g, err)
-    # correlators per channel (one configuration: translation-averaged VEV)
-    for g in range(len(CODES)):
-        s = _tilde_sign(CODES[g])
-        args = [ctx.dev(v[None]) for v in (Lf[g], s * Lf[g], Lb[g], s * Lb[g])]
+    # correlators per channel (one configuration: translation-averaged VEV), the
+    # source side taking the library's loops of Gamma~
+    for g in range(NC):
+        args = [ctx.dev(v[None]) for v in (Lf[g], Lf[NC + g], Lb[g], Lb[NC + g])]
         C, Cf, dC, four = [a.cpu().numpy() for a in ctx.correlator(*args)]
-        rC, rCf, rdC, _ = oracle.correlator(Lf_o[g][None], s * Lf_o[g][None], Lb_o[g][None], s * Lb_o[g][None])
+        rC, rCf, rdC, _ = oracle.correlator(Lf_o[g][None], Lf_o[NC + g][None], Lb_o[g][None], Lb_o[NC + g][None])
         # 1e-10 of the correlator, plus the FP64 rounding floor of the VEV-subtracted
         # products <L Lt> - <L><Lt> (both sides hit it when C is far below |L|^2)
         floor = 64 * np.finfo(float).eps * max(np.abs(Lf_o[g]).max(), np.abs(Lb_o[g]).max()) ** 2
@@ -376,18 +395,20 @@ def test_connected_correlator_and_noise_reduced_estimator(disco, method, blk):
 
 
 def test_bench_configuration_perambulators_sampled(disco):
-    """The benchmark's configuration on its full 16^3 x 32 workload: BF16-stored
-    BiCGStab with reliable updates, 64 lanes fed from one queue, projections of
-    the handed-over lanes; D on one timeslice (128 sources through 64 lanes)
-    and D_Lambda on one packing set (four timeslices per solve).  Sampled
-    columns tau(t,t)[:, :, i, alpha] against the oracle's own CGNR solves of
-    those sources (D_Lambda unpacked, one timeslice at a time).
+    """The benchmark's solver configuration on the full 16^3 x 32 workload:
+    BF16-stored BiCGStab with reliable updates, 64 lanes fed from one queue,
+    projections of the handed-over lanes; D on one timeslice (128 sources
+    through 64 lanes) and D_Lambda on one packing set (four timeslices per
+    solve).  Both sides take the same seeded smearing vectors (the projection
+    V^+ D^-1 V is defined for any V; the Laplacian eigenvectors are checked on
+    their own), and sampled columns tau(t,t)[:, :, i, alpha] are compared with
+    the oracle's own CGNR solves of those sources (D_Lambda unpacked, one
+    timeslice at a time).
 
     Tolerance: both sides stop at a true relative residual (1e-10 here, 1e-11
     for the oracle), so |tau - tau_ref| <= |D^-1| 1e-10 with unit sources; the
-    bound 1e-7 of max|tau_ref| allows |D^-1| up to 1e3 (observed: 1.6e-11 for
-    D, 3e-13 for D_Lambda).  Any wrong lane, source or sink timeslice gives an
-    error of order one."""
+    bound 1e-7 of max|tau_ref| allows |D^-1| up to 1e3.  Any wrong lane, source
+    or sink timeslice gives an error of order one."""
     pre = synth.PRESETS["prec_16x16x16x32"]
     dims = pre.dims
     Lx, Ly, Lz, Lt = dims
@@ -396,8 +417,8 @@ def test_bench_configuration_perambulators_sampled(disco):
     _say("bench configuration, sampled perambulators")
     U = synth.gauge_field(dims, pre.eps, pre.seed)
     ctx = _ctx(disco, dims, U, pre.kappa, pre.csw)
-    ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
-    Vev, _ = ctx.laplace_eigvecs(nv, 1e-11)
+    Vn = synth.random_colour_vectors(Lt, nv, Vs, 77)
+    Vev = ctx.dev(Vn)
     cut = synth.tiling_cuts(dims, pre.block)
     dom = ctx.domains(cut)
     P = ctx.params(method=disco.BICGSTAB_RU, tol=1e-10, inner_prec=disco.BF16, rhs_block=64)
@@ -411,7 +432,6 @@ def test_bench_configuration_perambulators_sampled(disco):
     ctx.perambulators_tt(Vev, pack, P, tau_b, dom)
     assert ctx.last_solves() == 4 * nv   # four timeslices per packed solve
     tf, tb = tau_f.cpu().numpy(), tau_b.cpu().numpy()
-    Vn = Vev.cpu().numpy()
     A = oracle.clover(U, dims, pre.kappa, pre.csw)
     for tau, c, ts in ((tf, None, (t0,)), (tb, cut, (t0, t0 + 2 * layer))):
         for t in ts:
@@ -424,21 +444,31 @@ def test_bench_configuration_perambulators_sampled(disco):
                 assert err < 1e-7
     # timeslices outside the masks are not written
     assert np.abs(tf[t0 + 1]).max() == 0 and np.abs(tb[t0 + 1]).max() == 0
-    # the bench's loops and correlators on these perambulators, against the
-    # oracle's on the same tau (fixed-order traces and products)
-    Lf = ctx.loops(tau_f, CODES).cpu().numpy()
-    Lb = ctx.loops(tau_b, CODES).cpu().numpy()
-    for g, c in enumerate(CODES):
-        gm = oracle.channel_matrix(c)
-        for L, tau in ((Lf, tf), (Lb, tb)):
-            ref = np.array([oracle.loop_from_tau(tau[t], gm) for t in range(Lt)])
-            assert np.abs(L[g] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0), (c, g)
-        sg = _tilde_sign(c)
-        args = [ctx.dev(v[None]) for v in (Lf[g], sg * Lf[g], Lb[g], sg * Lb[g])]
+
+
+def test_bench_shape_loops_and_correlators(disco):
+    """The bench's loop and correlator calls at its 16^3 x 32 shape (T = 32,
+    Nv = 32, the five channels and their Gamma~ loops from the library), on
+    seeded perambulators given to both sides, against the oracle's traces and
+    VEV-subtracted products."""
+    T, nv = 32, 32
+    rng = np.random.default_rng(78)
+    mk = lambda: rng.standard_normal((T, nv, 4, nv, 4)) + 1j * rng.standard_normal((T, nv, 4, nv, 4))
+    tf, tb = mk(), mk()
+    tb = tf + 0.05 * tb
+    ctx = disco.Context((2, 2, 2, T), BC)
+    Lf = ctx.loops(ctx.dev(tf), CODES + TCODES).cpu().numpy()
+    Lb = ctx.loops(ctx.dev(tb), CODES + TCODES).cpu().numpy()
+    Lf_o = oracle.loops(tf, CODES + TCODES)
+    Lb_o = oracle.loops(tb, CODES + TCODES)
+    assert _rel(Lf, Lf_o) < 1e-13 and _rel(Lb, Lb_o) < 1e-13
+    for g in range(NC):
+        args = [ctx.dev(v[None]) for v in (Lf_o[g], Lf_o[NC + g], Lb_o[g], Lb_o[NC + g])]
         C, Cf, dC, four = [x.cpu().numpy() for x in ctx.correlator(*args)]
-        rC, rCf, rdC, _ = oracle.correlator(Lf[g][None], sg * Lf[g][None], Lb[g][None], sg * Lb[g][None])
-        floor = 64 * np.finfo(float).eps * max(np.abs(Lf[g]).max(), np.abs(Lb[g]).max()) ** 2
+        rC, rCf, rdC, rfour = oracle.correlator(Lf_o[g][None], Lf_o[NC + g][None], Lb_o[g][None],
+                                                Lb_o[NC + g][None])
+        floor = 64 * np.finfo(float).eps * max(np.abs(Lf_o[g]).max(), np.abs(Lb_o[g]).max()) ** 2
         tol = 1e-10 * np.abs(rC).max() + floor
-        for got, ref in ((C, rC), (Cf, rCf), (dC, rdC)):
-            assert np.abs(got - ref).max() <= tol, c
+        for got, ref in ((C, rC), (Cf, rCf), (dC, rdC), (four, rfour)):
+            assert np.abs(got - ref).max() <= tol, CODES[g]
         assert np.abs(four.sum(axis=0) - C).max() <= floor

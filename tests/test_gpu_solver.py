@@ -325,3 +325,40 @@ def test_reliable_updates_lane_refill(disco, inner):
             continue
         d = np.linalg.norm(sol[3][k] - sol[11][k]) / np.linalg.norm(sol[11][k])
         assert d < 1e4 * tol, (k, d)  # a lane mix-up would show at O(1)
+
+
+@pytest.mark.parametrize("fallback", [1, 0])
+def test_reliable_updates_queue_survives_the_fallback(disco, fallback):
+    """Eleven right-hand sides through 3 lanes with an inner iteration cap far
+    below what a solve needs, so the first wave stops early.  The lanes in
+    flight go to the FP64 fallback (or, without it, come back unconverged), and
+    the rest of the queue runs on in a fresh Krylov process instead of coming
+    back as x = 0: with the fallback every right-hand side meets the tolerance
+    by the oracle's FP64 residual; without it every one has been worked on and
+    reports its true residual."""
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.124, 1.2
+    U = synth.gauge_field(dims, 0.3, 73)
+    A = oracle.clover(U, dims, kappa, csw)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, csw)
+    b = synth.random_spinor(ctx.V, 11, 74)
+    tol = 1e-10
+    P = ctx.params(method=disco.BICGSTAB_RU, tol=tol, inner_prec=disco.BF16, rhs_block=3, max_iter=4,
+                   fallback=fallback)
+    x, st = ctx.solve_multi_rhs(ctx.dev(b), P, allow_noconv=True)
+    x = x.cpu().numpy()
+    rr = _true_rel_res(U, A, dims, kappa, b, x)
+    _say("  queue with fallback=%d: residuals %s, fallback %s" %
+         (fallback, ["%.1e" % r for r in rr], [s.fallback_used for s in st]))
+    for k in range(11):
+        assert abs(rr[k] - st[k].true_rel_residual) <= max(1e-2 * rr[k], 2e-15)
+        assert st[k].iters > 0
+    if fallback:
+        assert rr.max() <= tol * 1.05
+        assert all(s.converged and s.fallback_used == 1 for s in st)
+    else:
+        assert rr.max() < 0.9          # every one was worked on, none returned as x = 0
+        assert all(s.fallback_used == 0 for s in st)
+        assert all(s.converged == (r <= tol) for s, r in zip(st, rr))
