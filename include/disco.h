@@ -140,6 +140,20 @@ int disco_domains_destroy(disco_domains* dom);
  * rounded to FP32, FP32 accumulation) or DISCO_BF16 (inputs rounded to BF16
  * storage, FP32 links and accumulation).  in and out must not overlap. */
 int disco_dirac_apply(disco_ctx* ctx, int prec, int dagger, int nrhs, const void* in, void* out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): disco_dirac_apply
+ * without any allocation.  The two native-layout staging blocks live in a
+ * fixed 256 MiB device array of the library, one per GPU, held until the
+ * process ends; right-hand sides are processed in chunks that fit (at most 64
+ * per launch).  EINVAL when a single right-hand side does not fit: its native
+ * block, 192 V bytes in FP64, 96 V in FP32, 48 V in BF16, must not exceed
+ * 128 MiB less 256 bytes (so 24^3 x 48 fits in every precision, 32^3 x 64 in
+ * FP32 and BF16).
+ * Every call on one GPU shares that array: calls that overlap on one GPU (two
+ * contexts or streams on the same device) race and must be serialised by the
+ * caller.  Launches of this call are not profiled.  Otherwise as
+ * disco_dirac_apply, with the same kernels and results. */
+int disco_dirac_apply_noalloc(disco_ctx* ctx, int prec, int dagger, int nrhs, const void* in, void* out);
 /* Same with the domain-restricted operator D_Lambda of the Domain
  * decomposition subsection: D restricted to the fields inside each domain of
  * `dom` (Dirichlet faces): every hop across a cut face is dropped, A(x) is

@@ -74,6 +74,7 @@ _SIGS = {
     "disco_domains_destroy": ([P], I),
     "disco_dirac_apply": ([P, I, I, I, P, P], I),
     "disco_dirac_block_apply": ([P, P, I, I, I, P, P], I),
+    "disco_dirac_apply_noalloc": ([P, I, I, I, P, P], I),
     "disco_native_bytes": ([P, I, I], LL),
     "disco_to_native": ([P, I, I, P, P], I),
     "disco_from_native": ([P, I, I, P, P], I),
@@ -320,6 +321,13 @@ class Context:
         n = psi.shape[0]
         out = self.empty_spinors(n) if out is None else out
         self._chk(lib().disco_dirac_apply(self.h, prec, int(dagger), n, _dptr(psi), _dptr(out)))
+        return out
+
+    def dirac_apply_noalloc(self, psi, prec=F64, dagger=False, out=None):
+        """As dirac_apply, through the entry point that allocates no device memory."""
+        n = psi.shape[0]
+        out = self.empty_spinors(n) if out is None else out
+        self._chk(lib().disco_dirac_apply_noalloc(self.h, prec, int(dagger), n, _dptr(psi), _dptr(out)))
         return out
 
     def dirac_block_apply(self, dom: Domains, psi, prec=F64, dagger=False, out=None):

@@ -281,6 +281,9 @@ long long solve_fed(disco_ctx* ctx, const disco_domains* dom, const disco_solver
 bool eo_supported(const disco_ctx* ctx);
 int stencil_spb(int n);                    // sites per stencil block
 void build_traversal(disco_ctx* ctx);
+// resolve the device address of the no-allocation scratch array on `device`
+// (the current device), once per device
+void scratch_bind(int device);
 void stencil_launch(disco_ctx* ctx, const StencilCall& c);
 size_t native_bytes(const disco_ctx* ctx, int prec, int nrhs);
 void to_native(disco_ctx* ctx, int prec, int nrhs, const void* in, void* out);

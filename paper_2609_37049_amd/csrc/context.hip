@@ -347,6 +347,7 @@ int disco_create(const int dims[4], const int bc[4], int device, disco_ctx** out
         REQUIRE(dims[0] <= 255 && dims[1] <= 255 && dims[2] <= 255 && dims[3] <= 255, DISCO_EINVAL,
                 "extents above 255 are not supported");
         disco::build_traversal(ctx);
+        disco::scratch_bind(device);
     });
     if (rc != DISCO_OK) {
         create_err = ctx->err;
