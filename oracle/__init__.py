@@ -203,28 +203,28 @@ def site_apply(M: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """Site-local 12x12 matrices M [V][12][12] on spinors [..][V][4][3]."""
     sh = psi.shape
     flat = psi.reshape(sh[:-2] + (12,))
-    return np.einsum("sij,...sj->...si", M, flat).reshape(sh)
-
-
-def hopping(U, A, dims, bc, kappa, psi, cut=None) -> np.ndarray:
-    """H psi for D = A - kappa H (with D_Lambda's hops when cut is given), from
-    the definition: H = (A - D) / kappa."""
-    return (site_apply(A, psi) - dirac(U, A, dims, bc, kappa, psi, cut)) / kappa
+    return np.matmul(M, flat[..., None])[..., 0].reshape(sh)
 
 
 def eo_piece(U, A, dims, bc, kappa, parity, ca, cg, cb, psi, aux=None, cut=None, Ainv=None) -> np.ndarray:
     """out(x) = ca aux(x) + A(x)^-1 [cg aux(x) + cb (H psi_{1-p})(x)] at the sites x
     of parity p, zero at the others, with psi_{1-p} = psi on the sites of the
-    other parity only.  With the coefficients of the solver these are the
-    pieces of M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, of its source
+    other parity only and H the hopping sum of D = A - kappa H (with D_Lambda's
+    hops when cut is given).  A is site-local and psi_{1-p} vanishes at the
+    sites of parity p, so there H psi_{1-p} = -(D psi_{1-p}) / kappa.  With the
+    coefficients of the solver these are the pieces of
+    M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, of its source
     A_ee^-1 (b_e + kappa H_eo A_oo^-1 b_o) and of the odd reconstruction
     A_oo^-1 (b_o + kappa H_oe x_e).  Ainv: A^-1 per site when already at hand."""
     par = site_parity(dims)
+    on = par == parity
     pin = np.where((par == 1 - parity)[:, None, None], psi, 0)
-    h = hopping(U, A, dims, bc, kappa, pin, cut)
+    h = -dirac(U, A, dims, bc, kappa, pin, cut)[..., on, :, :] / kappa
     a = np.zeros_like(psi) if aux is None else aux
-    out = ca * a + site_apply(np.linalg.inv(A) if Ainv is None else Ainv, cg * a + cb * h)
-    return np.where((par == parity)[..., :, None, None], out, 0)
+    Ai = (np.linalg.inv(A) if Ainv is None else Ainv)[on]
+    out = np.zeros_like(psi)
+    out[..., on, :, :] = ca * a[..., on, :, :] + site_apply(Ai, cg * a[..., on, :, :] + cb * h)
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -68,7 +68,7 @@ def _round(t, prec, disco):
     return t
 
 
-def _check_pieces(disco, ctx, U, A, Ainv, dims, kappa, cut, dom, prec, n, seed, lanes, tag):
+def _check_pieces(disco, ctx, U, A, Ainv, dims, kappa, cut, dom, prec, n, seed, lanes, tag, production_only=False):
     V = ctx.V
     psi = _round(synth.random_spinor_device(V, n, seed), prec, disco)
     aux = _round(synth.random_spinor_device(V, n, seed + 1), prec, disco)
@@ -78,11 +78,17 @@ def _check_pieces(disco, ctx, U, A, Ainv, dims, kappa, cut, dom, prec, n, seed, 
     aux2_h = aux2[lanes].cpu().numpy()
     par = oracle.site_parity(dims)
     worst = {}
+    refs_by_coef = {}
     for name, p, ca, cg, cb, epi in _pieces(disco, kappa):
+        if production_only and epi == disco.EPI_NORM | disco.EPI_DOTIN:
+            continue   # an epilogue the even-odd solvers do not launch
         out_t, sums = ctx.dirac_eo_apply(psi, p, ca, cg, cb, prec, dom, aux, aux2, epi)
         out = out_t[lanes].cpu().numpy()
         del out_t
-        ref = oracle.eo_piece(U, A, dims, BC, kappa, p, ca, cg, cb, psi_h, aux_h, cut, Ainv)
+        key = (p, ca, cg, cb)
+        if key not in refs_by_coef:
+            refs_by_coef[key] = oracle.eo_piece(U, A, dims, BC, kappa, p, ca, cg, cb, psi_h, aux_h, cut, Ainv)
+        ref = refs_by_coef[key]
         err = np.abs(out - ref).max() / np.abs(ref).max()
         worst[name] = err
         assert err < TOL[prec], (tag, name, err)
@@ -179,7 +185,7 @@ def test_even_odd_pieces_16x16x16x32_all_lanes(disco):
             _say("even-odd pieces 16x16x16x32, 64 rhs, prec", prec, "masked", masked)
             _check_pieces(disco, ctx, U, A, Ainv, pre.dims, pre.kappa, cut if masked else None,
                           dom if masked else None, prec, 64, 300 + prec, list(range(64)),
-                          "16x16x16x32 prec %d masked %d" % (prec, masked))
+                          "16x16x16x32 prec %d masked %d" % (prec, masked), production_only=True)
 
 
 @pytest.mark.timeout(900)
@@ -197,4 +203,4 @@ def test_even_odd_pieces_24x24x24x48_sampled_lanes(disco):
             _say("even-odd pieces 24x24x24x48, 64 rhs, prec", prec, "masked", masked)
             _check_pieces(disco, ctx, U, A, Ainv, pre.dims, pre.kappa, cut if masked else None,
                           dom if masked else None, prec, 64, 400 + prec, lanes,
-                          "24x24x24x48 prec %d masked %d" % (prec, masked))
+                          "24x24x24x48 prec %d masked %d" % (prec, masked), production_only=True)
