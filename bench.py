@@ -1,25 +1,30 @@
 """Benchmark of the hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--method ru|dc]
-                    [--workload prec_16x16x16x32|batch_24x24x24x48] [--no-cpu-baseline]
+                    [--workload batch_24x24x24x48|prec_16x16x16x32] [--nv-per-step N]
+                    [--no-cpu-baseline] [--no-legs]
 
-Workload (default): the mixed-precision distillation set-up on a 16^3 x 32
-lattice (synthetic links exp(i 0.25 sum r_a T_a), 5 APE steps alpha = 0.5 for
-the Laplacian, Wilson-clover kappa = 0.125, csw = 1.5, antiperiodic time,
-Nv = 32 eigenvectors per timeslice, domains 4^3 x 8), solved to true relative
-residual 1e-10 by BiCGStab with BF16-stored, FP32-arithmetic inner solves and
-FP64 reliable updates (--method dc: inside FP64 defect correction).
---workload batch_24x24x24x48 runs the same step on the 24^3 x 48 batching
-shape (kappa = 0.126, csw = 1.6, Nv = 64, domains 6 x 6 x 8 x 12).
+Workload (default): the batching configuration, a 24^3 x 48 lattice
+(synthetic links exp(i 0.25 sum r_a T_a), 5 APE steps alpha = 0.5 for the
+Laplacian, Wilson-clover kappa = 0.126, csw = 1.6, antiperiodic time, Nv = 64
+eigenvectors per timeslice, domains 6 x 6 x 8 x 12), solved to true relative
+residual 1e-10 by BiCGStab with BF16-stored, FP32-arithmetic inner solves on
+the even-odd Schur complement and FP64 reliable updates (--method dc: inside
+FP64 defect correction), 64 right-hand sides per launch fed from one queue.
+--workload prec_16x16x16x32 runs the same step on the 16^3 x 32 precision
+shape (kappa = 0.125, csw = 1.5, Nv = 32, domains 4^3 x 8).
 
 One step is one batch of the whole hot path: the four timeslices of one
-multi-site packing set (one timeslice per temporal layer of the partition) --
-sources, full-operator solves (4 x 4 x Nv RHS), packed domain-restricted
-solves (4 x Nv solves carrying 4 x 4 x Nv logical RHS), perambulator
-projection, loops for five Gamma channels, and the full / factorised /
-subtracted correlators.  The value is logical RHS (full + restricted) per
-second over the timed steps; set-up (clover term, APE, eigenvectors) is timed
-once before and reported beside it.
+multi-site packing set (one timeslice per temporal layer of the partition)
+for one group of eigenvectors (16 of the 64 at 24^3 x 48, all 32 at
+16^3 x 32) -- sources, full-operator solves (4 x 4 x group RHS), packed
+domain-restricted solves (4 x group solves carrying 4 x 4 x group logical
+RHS), perambulator projection, loops for five Gamma channels and their
+Gamma-tilde (formed by the library), and the full / factorised / subtracted
+correlators.  Steps cycle through the packing sets and eigenvector groups.
+The value is logical RHS (full + restricted) per second over the timed steps,
+with the full-operator and D_Lambda rates beside it; set-up (clover term,
+APE, eigenvectors, autotuning) is timed once before and reported beside it.
 
 Prints one JSON line.
 """
@@ -290,6 +295,7 @@ def cpu_baseline(pre, nrhs=2):
 
 
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -299,8 +305,11 @@ def main():
     ap.add_argument("--method", choices=["ru", "dc"], default="ru",
                     help="BiCGStab with reliable updates (default) or inside FP64 defect correction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the stencil measurement at 24^3x48")
-    ap.add_argument("--workload", choices=["prec_16x16x16x32", "batch_24x24x24x48"], default="prec_16x16x16x32")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the solver comparison and the region-schedule legs after the timed steps")
+    ap.add_argument("--nv-per-step", type=int, default=0,
+                    help="eigenvectors per step (a divisor of Nv; default Nv/4 at 24^3x48, Nv at 16^3x32)")
+    ap.add_argument("--workload", choices=["batch_24x24x24x48", "prec_16x16x16x32"], default="batch_24x24x24x48")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solves of different right-hand sides are independent, so "
@@ -316,6 +325,8 @@ def main():
     dims = pre.dims
     T = dims[3]
     codes = [d.G_1, d.G_5, d.G_X, d.G_Y, d.G_Z]
+    nc = len(codes)
+    loop_codes = codes + [c | d.G_TILDE for c in codes]   # Gamma and Gamma~ = g4 Gamma^+ g4, from the library
     torch.cuda.set_device(0)
     U = synth.gauge_field(dims, pre.eps, pre.seed)
     ctx = d.Context(dims, pre.bc, 0)
@@ -330,53 +341,72 @@ def main():
     dom = ctx.domains(cut)
     inner = d.BF16 if args.inner == "bf16" else d.F32
     tuned, tune_cost = ctx.autotune(inner)
+    nv = pre.nv
+    nvs = args.nv_per_step or (nv // 4 if args.workload == "batch_24x24x24x48" else nv)
+    if nv % nvs:
+        raise SystemExit("--nv-per-step must divide Nv = %d" % nv)
+    nq = nv // nvs
+    # the eigenvector groups of the steps, each [T][nvs][Vs][3] (resident before timing)
+    Vq = [Vev[:, q * nvs:(q + 1) * nvs].contiguous() for q in range(nq)]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print("set-up done in %.1f s (rhs block %d)" % (setup_s, tuned), file=sys.stderr, flush=True)
 
     method = d.BICGSTAB_RU if args.method == "ru" else d.BICGSTAB_DC
     P = ctx.params(method=method, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block)
-    nv = pre.nv
     dev = "cuda:0"
-    tau_f = torch.zeros((T, nv, 4, nv, 4), dtype=torch.complex128, device=dev)
-    tau_b = torch.zeros_like(tau_f)
+    # perambulators tau(t,t) per eigenvector group, filled set by set
+    tau_f = [torch.zeros((T, nvs, 4, nvs, 4), dtype=torch.complex128, device=dev) for _ in range(nq)]
+    tau_b = [torch.zeros_like(tau_f[0]) for _ in range(nq)]
     layer = pre.block[3]
     groups = [sum(1 << (g + layer * k) for k in range(T // layer)) for g in range(layer)]
-    sign = torch.tensor([1.0, -1.0, -1.0, -1.0, -1.0], dtype=torch.float64, device=dev)[:, None]
+    combos = [(g, q) for g in range(len(groups)) for q in range(nq)]
 
     def step(k):
-        msk = groups[k % len(groups)]
-        a1 = ctx.perambulators_tt(Vev, msk, P, tau_f)
+        g, q = combos[k % len(combos)]
+        msk = groups[g]
+        ta = time.perf_counter()
+        a1 = ctx.perambulators_tt(Vq[q], msk, P, tau_f[q])
         n_full = ctx.last_solves()
-        a2 = ctx.perambulators_tt(Vev, msk, P, tau_b, dom)
+        tb = time.perf_counter()
+        a2 = ctx.perambulators_tt(Vq[q], msk, P, tau_b[q], dom)
         n_blk = ctx.last_solves()
-        Lf = ctx.loops(tau_f, codes)
-        Lb = ctx.loops(tau_b, codes)
-        for g in range(len(codes)):
-            ctx.correlator(Lf[g:g + 1].contiguous(), (sign[g] * Lf[g:g + 1]).contiguous(),
-                           Lb[g:g + 1].contiguous(), (sign[g] * Lb[g:g + 1]).contiguous())
-        logical = 4 * nv * bin(msk).count("1") * 2
-        return logical, n_full, n_blk, max(a1.true_rel_residual, a2.true_rel_residual), a1, a2
+        tc = time.perf_counter()
+        # partial loops over this group's eigenvectors, for the Gamma's and their
+        # Gamma~'s, and the full / factorised / subtracted correlators of them
+        Lf = ctx.loops(tau_f[q], loop_codes)
+        Lb = ctx.loops(tau_b[q], loop_codes)
+        for c in range(nc):
+            ctx.correlator(Lf[c:c + 1], Lf[nc + c:nc + c + 1], Lb[c:c + 1], Lb[nc + c:nc + c + 1])
+        torch.cuda.synchronize()
+        logical = 4 * nvs * bin(msk).count("1")
+        return (logical, n_full, n_blk, max(a1.true_rel_residual, a2.true_rel_residual), a1, a2,
+                tb - ta, tc - tb)
 
     for k in range(args.warmup):
         step(k)
         print("warmup step %d done" % k, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rhs = 0
-    solves = 0
+    rhs_full = rhs_blk = solves_full = solves_blk = 0
+    t_full = t_blk = 0.0
     worst = 0.0
     iters = 0
     for k in range(args.warmup, args.warmup + args.steps):
-        logical, nf, nb, res, a1, a2 = step(k)
-        rhs += logical
-        solves += nf + nb
+        logical, nf, nb, res, a1, a2, dtf, dtb = step(k)
+        rhs_full += logical
+        rhs_blk += logical
+        solves_full += nf
+        solves_blk += nb
+        t_full += dtf
+        t_blk += dtb
         worst = max(worst, res)
         iters += a1.iters + a2.iters
-        print("timed step %d: %d logical RHS, %d solves, worst residual %.2e" % (k, logical, nf + nb, res),
+        print("timed step %d: %d logical RHS, %d solves, worst residual %.2e" % (k, 2 * logical, nf + nb, res),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    rhs = rhs_full + rhs_blk
     # The production steps above run their inner iterations as HIP graphs; the
     # per-launch stencil times come from one more pass of a step's full-operator
     # solves (the dominant launches: the unmasked stencil; the D_Lambda solves use
@@ -385,7 +415,8 @@ def main():
     ctx.profile_reset()
     ctx.profile_stride(1)
     ctx.profile_enable(True)
-    ctx.perambulators_tt(Vev, groups[(args.warmup + args.steps) % len(groups)], P, tau_f)
+    g_next, q_next = combos[(args.warmup + args.steps) % len(combos)]
+    ctx.perambulators_tt(Vq[q_next], groups[g_next], P, tau_f[q_next])
     ctx.profile_enable(False)
     # dominant kernel: the inner-precision stencil family with the most launches
     # (the even-odd half-lattice stencil when every extent is even)
@@ -410,10 +441,12 @@ def main():
     lat = "x".join(map(str, dims))
     big = args.workload != "prec_16x16x16x32"
     roof = stencil_roofline(kernel_tag, nl, ms, by, sites, blk, "%s/n%d" % (kernel_tag, blk) + ("/" + lat if big else ""))
-    comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
-    slab = slab_schedule_cost(ctx, d, Vev, inner, args.rhs_block or tuned, method)
-    # the stencil at the batching shape (already the workload's own shape when big)
-    large = None if (args.no_large or big) else stencil_at_batch_shape(d, inner, blk)
+    comparison = nn_roof = slab = None
+    if not args.no_legs:
+        comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
+        slab = slab_schedule_cost(ctx, d, Vev, inner, args.rhs_block or tuned, method, nv_sub=2 if big else 4)
+    # the stencil at the batching shape when the workload is the smaller one
+    large = None if (args.no_legs or big) else stencil_at_batch_shape(d, inner, blk)
     if large:
         print("24^3x48 stencil: %.1f GB/s over %d launches" % (large["achieved"], large["launches_timed"]),
               file=sys.stderr, flush=True)
@@ -422,15 +455,26 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "%s Wilson-clover kappa=%g csw=%g, Nv=%d, domains %s, "
+        "config": {"workload": "%s Wilson-clover kappa=%g csw=%g, Nv=%d (%d per step), domains %s, "
                                "BiCGStab %s-storage/FP32 inner, %s, to FP64 true residual 1e-10" % (
-                                   lat, pre.kappa, pre.csw, nv, "x".join(map(str, pre.block)),
+                                   lat, pre.kappa, pre.csw, nv, nvs, "x".join(map(str, pre.block)),
                                    args.inner, "reliable updates" if args.method == "ru" else "FP64 defect correction"),
-                   "lattice": lat, "nv": nv, "rhs_block": args.rhs_block or tuned,
+                   "lattice": lat, "kappa": pre.kappa, "csw": pre.csw, "nv": nv, "nv_per_step": nvs,
+                   "domains": "x".join(map(str, pre.block)), "rhs_block": args.rhs_block or tuned,
                    "autotune_us_per_rhs_iter": {str(k): round(v, 3) for k, v in tune_cost.items()},
                    "inner_storage": args.inner, "hip_graphs": True, "method": args.method,
                    "outer": "f64", "logical_rhs_per_step": rhs // max(args.steps, 1),
-                   "solves_per_step": solves // max(args.steps, 1)},
+                   "solves_per_step": (solves_full + solves_blk) // max(args.steps, 1),
+                   "step": "one packing set (%d timeslices, one per temporal layer) x %d eigenvectors x 4 spins: "
+                           "sources, full-operator solves, packed D_Lambda solves, projections, loops of 5 "
+                           "Gamma and their Gamma-tilde, full/factorised/subtracted correlators"
+                           % (T // layer, nvs)},
+        "rates": {"full_operator_rhs_per_s": round(rhs_full / t_full, 2) if t_full > 0 else None,
+                  "d_lambda_logical_rhs_per_s": round(rhs_blk / t_blk, 2) if t_blk > 0 else None,
+                  "d_lambda_packed_solves_per_s": round(solves_blk / t_blk, 2) if t_blk > 0 else None,
+                  "full_operator_s": round(t_full, 3), "d_lambda_s": round(t_blk, 3),
+                  "note": "value counts each packed D_Lambda solve as the %d logical right-hand sides it carries"
+                          % (T // layer)},
         "roofline": roof,
         "roofline_24x24x24x48": large,
         "solver_comparison": comparison,
@@ -444,6 +488,7 @@ def main():
     if not args.no_cpu_baseline:
         # about 15 s of host work at 16^3x32; one RHS (about 60 s) at 24^3x48
         out["cpu_baseline"] = cpu_baseline(pre, 1 if big else 2)
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 
