@@ -365,6 +365,30 @@ int disco_slab_sets(int T, int delta, int* nsets, unsigned long long* masks);
  * subtracted correlator: pass them as L_blk / Lt_blk to disco_correlator. */
 int disco_loops_slab(disco_ctx* ctx, const void* Vev, int nv, const double* w, const int* gammas, int ngamma,
                      int delta, const disco_solver_params* p, void* L, void* tau_out, disco_solver_stats* agg);
+/* The same schedule with the paper's open time boundary (Results: the ensemble
+ * has open boundary conditions in time), read as one more cut: no hop crosses
+ * the face between t = T-1 and t = 0, in the full operator as in every region
+ * (no boundary improvement terms).  The slab of x0 is then clipped at the
+ * boundaries, Lambda(x0) = {t : |t - x0| <= (delta-1)/2, 0 <= t < T}, and the
+ * sets of disco_slab_sets_open group operator times whose slabs are disjoint
+ * on the open line (distance |x0 - y0| >= delta, not taken around the wrap).
+ * The loops of the full operator with the same boundary come from
+ * disco_loops_distill with domains whose only cut is cut[3][T-1].  The paper
+ * measures in a bulk window away from the boundaries (Cost section); pass
+ * such a window as y0_set to disco_correlator.  Arguments as above. */
+int disco_slab_sets_open(int T, int delta, int* nsets, unsigned long long* masks);
+int disco_loops_slab_open(disco_ctx* ctx, const void* Vev, int nv, const double* w, const int* gammas, int ngamma,
+                          int delta, const disco_solver_params* p, void* L, void* tau_out, disco_solver_stats* agg);
+/* The noise-reduced estimator spliced by separation (Results, analysis with
+ * standard distillation): C^NR(dt) = C^(c)(dt) + dC_Delta(dt) with, at each
+ * separation dt, the widest slab width Delta of deltas[0..ndelta-1] below dt
+ * (with widths 7, 9, 11, 13 this is the paper's choice: 7 for dt = 8, 9;
+ * 9 for 10, 11; 11 for 12, 13; 13 from 14 on).  Cc (host, [T] complex128, the
+ * connected correlator of disco_connected), dC (host, [ndelta][T] complex128,
+ * the subtracted correlators of disco_correlator with the slab loops of each
+ * width), out (host, [T] complex128): NaN at separations no width is below.
+ * Host only. */
+int disco_nr_splice(const double* Cc, const double* dC, const int* deltas, int ndelta, int T, double* out);
 /* Gaussian distillation profiles (the Gaussian-profiled subsection): the
  * diagonal elemental weight |g_k(lambda)|^2 with g_k(lambda) =
  * exp(-lambda^2 / (2 (0.8 omega_k)^2)), i.e. w = exp(-lambda^2 / (0.8 omega)^2),

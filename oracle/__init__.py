@@ -485,27 +485,59 @@ def correlator(L_full, Lt_full, L_blk, Lt_blk, y0s=None, vev_mode=1):
 # the paper's region schedule and Gaussian profiles
 # --------------------------------------------------------------------------
 
-def slab_cut(dims, x0: int, delta: int) -> np.ndarray:
+def slab_cut(dims, x0: int, delta: int, open_time: bool = False) -> np.ndarray:
     """Cut masks of the partition whose region around operator time x0 is the
     temporal slab {t : |t - x0| <= h} (mod T), h = (delta-1)/2, over all space
-    (Domain decomposition subsection): faces after x0+h and after x0-h-1."""
+    (Domain decomposition subsection): faces after x0+h and after x0-h-1.
+    With open_time (the open boundary in time of the paper's ensemble, read as
+    one more cut): the face between T-1 and 0 is cut and the slab is clipped
+    at the boundaries instead of wrapping."""
     T = dims[3]
     h = (delta - 1) // 2
     cut = np.zeros((4, max(dims)), dtype=np.uint8)
+    if open_time:
+        cut[3, T - 1] = 1
+        if x0 + h < T - 1:
+            cut[3, x0 + h] = 1
+        if x0 - h - 1 >= 0:
+            cut[3, x0 - h - 1] = 1
+        return cut
     cut[3, (x0 + h) % T] = 1
     cut[3, (x0 - h - 1) % T] = 1
     return cut
 
 
-def slab_loops(U, A, dims, bc, kappa, Vt, delta: int, codes, w=None, tol=1e-13):
+def open_time_cut(dims) -> np.ndarray:
+    """Cut masks of the open time boundary alone: the full operator of an
+    ensemble with open boundary conditions in time."""
+    cut = np.zeros((4, max(dims)), dtype=np.uint8)
+    cut[3, dims[3] - 1] = 1
+    return cut
+
+
+def slab_loops(U, A, dims, bc, kappa, Vt, delta: int, codes, w=None, tol=1e-13, open_time=False):
     """L[g][x0]: the loop of D_Lambda(x0)^-1 at x0 for every operator time x0,
     each solved on its own (no multi-site packing)."""
     T = dims[3]
     nv = Vt.shape[1]
     tau = np.empty((T, nv, 4, nv, 4), dtype=np.complex128)
     for x0 in range(T):
-        tau[x0] = perambulator_tt(U, A, dims, bc, kappa, Vt, x0, slab_cut(dims, x0, delta), tol)
+        tau[x0] = perambulator_tt(U, A, dims, bc, kappa, Vt, x0, slab_cut(dims, x0, delta, open_time), tol)
     return loops(tau, codes, w), tau
+
+
+def nr_splice(Cc, dC_by_delta, deltas) -> np.ndarray:
+    """The noise-reduced estimator spliced by separation (Results, analysis with
+    standard distillation): C^NR(dt) = C^(c)(dt) + dC_Delta(dt), Delta the widest
+    of the given slab widths that is smaller than dt; NaN where none is."""
+    T = len(Cc)
+    out = np.full(T, np.nan + 0j, dtype=np.complex128)
+    for dt in range(T):
+        below = [k for k, d in enumerate(deltas) if d < dt]
+        if below:
+            k = max(below, key=lambda q: deltas[q])
+            out[dt] = Cc[dt] + dC_by_delta[k][dt]
+    return out
 
 
 def profile_weights(lam, omega: float) -> np.ndarray:

@@ -102,6 +102,10 @@ _SIGS.update({
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
     "disco_slab_sets": ([I, I, ctypes.POINTER(I), P], I),
     "disco_loops_slab": ([P, P, I, P, P, I, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
+    "disco_slab_sets_open": ([I, I, ctypes.POINTER(I), P], I),
+    "disco_loops_slab_open": ([P, P, I, P, P, I, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)],
+                              I),
+    "disco_nr_splice": ([P, P, P, I, I, P], I),
     "disco_profile_weights": ([P, ctypes.c_long, D, P], I),
     "disco_perambulators_all": ([P, P, I, ctypes.c_ulonglong, ctypes.POINTER(SolverParams), P,
                                  ctypes.POINTER(SolverStats)], I),
@@ -443,25 +447,40 @@ class Context:
                                             ctypes.byref(agg)))
         return L, tau, agg
 
-    def slab_sets(self, delta):
+    def slab_sets(self, delta, open_time=False):
         T = self.dims[3]
         n = I()
         m = (ctypes.c_ulonglong * T)()
-        rc = lib().disco_slab_sets(T, int(delta), ctypes.byref(n), ctypes.cast(m, P))
+        fn = lib().disco_slab_sets_open if open_time else lib().disco_slab_sets
+        rc = fn(T, int(delta), ctypes.byref(n), ctypes.cast(m, P))
         if rc != OK:
             raise DiscoError(rc, "bad slab width %r" % (delta,))
         return [int(m[k]) for k in range(n.value)]
 
-    def loops_slab(self, Vev, gammas, delta, params: SolverParams, w=None, want_tau=False):
+    def loops_slab(self, Vev, gammas, delta, params: SolverParams, w=None, want_tau=False, open_time=False):
         torch = _torch()
         T, nv = Vev.shape[0], Vev.shape[1]
         g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
         L = torch.empty((len(g), T), dtype=torch.complex128, device=Vev.device)
         tau = torch.empty((T, nv, 4, nv, 4), dtype=torch.complex128, device=Vev.device) if want_tau else None
         agg = SolverStats()
-        self._chk(lib().disco_loops_slab(self.h, _dptr(Vev), nv, _dptr(w), g.ctypes.data_as(P), len(g), int(delta),
-                                         ctypes.byref(params), _dptr(L), _dptr(tau), ctypes.byref(agg)))
+        fn = lib().disco_loops_slab_open if open_time else lib().disco_loops_slab
+        self._chk(fn(self.h, _dptr(Vev), nv, _dptr(w), g.ctypes.data_as(P), len(g), int(delta),
+                     ctypes.byref(params), _dptr(L), _dptr(tau), ctypes.byref(agg)))
         return L, tau, agg
+
+    @staticmethod
+    def nr_splice(Cc, dC, deltas):
+        """C^NR spliced by separation from host arrays: Cc [T], dC [len(deltas)][T]."""
+        Cc = np.ascontiguousarray(np.asarray(Cc, dtype=np.complex128))
+        dC = np.ascontiguousarray(np.asarray(dC, dtype=np.complex128))
+        dl = np.ascontiguousarray(np.asarray(deltas, dtype=np.int32))
+        out = np.empty_like(Cc)
+        rc = lib().disco_nr_splice(Cc.ctypes.data_as(P), dC.ctypes.data_as(P), dl.ctypes.data_as(P), len(dl),
+                                   len(Cc), out.ctypes.data_as(P))
+        if rc != OK:
+            raise DiscoError(rc, "bad splice arguments")
+        return out
 
     def perambulators_all(self, Vev, params: SolverParams, tmask=0):
         torch = _torch()

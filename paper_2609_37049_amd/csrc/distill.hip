@@ -1109,7 +1109,9 @@ int disco_loops_distill(disco_ctx* ctx, const disco_domains* dom, const void* Vi
 // "Subtraction method"; the width delta is odd).  Operator times whose slabs
 // are disjoint mod T (circular distance >= delta) share one multi-site solve
 // (the Cost section): they are grouped greedily in increasing x0.
-static std::vector<unsigned long long> slab_sets(int T, int delta) {
+// With an open time boundary the distance is not taken around the wrap (the
+// slabs are clipped at t = 0 and t = T-1 instead of wrapping).
+static std::vector<unsigned long long> slab_sets(int T, int delta, bool open = false) {
     std::vector<std::vector<int>> sets;
     for (int x0 = 0; x0 < T; x0++) {
         bool placed = false;
@@ -1117,7 +1119,7 @@ static std::vector<unsigned long long> slab_sets(int T, int delta) {
             bool ok = true;
             for (int y : set) {
                 const int d = std::abs(x0 - y);
-                if (std::min(d, T - d) < delta) ok = false;
+                if ((open ? d : std::min(d, T - d)) < delta) ok = false;
             }
             if (ok) {
                 set.push_back(x0);
@@ -1136,13 +1138,21 @@ static std::vector<unsigned long long> slab_sets(int T, int delta) {
     return masks;
 }
 
-int disco_slab_sets(int T, int delta, int* nsets, unsigned long long* masks) {
+static int slab_sets_abi(int T, int delta, bool open, int* nsets, unsigned long long* masks) {
     if (T < 1 || T > 64 || delta < 1 || delta % 2 == 0 || delta >= T || !nsets) return DISCO_EINVAL;
-    const auto m = slab_sets(T, delta);
+    const auto m = slab_sets(T, delta, open);
     *nsets = (int)m.size();
     if (masks)
         for (size_t k = 0; k < m.size(); k++) masks[k] = m[k];
     return DISCO_OK;
+}
+
+int disco_slab_sets(int T, int delta, int* nsets, unsigned long long* masks) {
+    return slab_sets_abi(T, delta, false, nsets, masks);
+}
+
+int disco_slab_sets_open(int T, int delta, int* nsets, unsigned long long* masks) {
+    return slab_sets_abi(T, delta, true, nsets, masks);
 }
 
 int disco_profile_weights(const double* lambda, long n, double omega, double* w) {
@@ -1152,8 +1162,9 @@ int disco_profile_weights(const double* lambda, long n, double omega, double* w)
     return DISCO_OK;
 }
 
-int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, const int* gammas, int ngamma, int delta,
-                     const disco_solver_params* P, void* L, void* tau_out, disco_solver_stats* agg) {
+static int loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, const int* gammas, int ngamma,
+                      int delta, bool open, const disco_solver_params* P, void* L, void* tau_out,
+                      disco_solver_stats* agg) {
     if (!ctx) return DISCO_EINVAL;
     void* tau = tau_out;
     std::vector<unsigned long long> sets;
@@ -1163,7 +1174,7 @@ int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, c
         REQUIRE(delta >= 1 && delta % 2 == 1 && delta < T, DISCO_EINVAL, "slab width must be odd and below T");
         REQUIRE(T <= 64, DISCO_EINVAL, "at most 64 timeslices");
         if (!tau) tau = ws_get(ctx, "ls_tau", sizeof(double2) * (size_t)T * nv * 4 * nv * 4);
-        sets = slab_sets(T, delta);
+        sets = slab_sets(T, delta, open);
     });
     if (rc != DISCO_OK) return rc;
     const int T = ctx->dims[3];
@@ -1179,9 +1190,16 @@ int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, c
         std::vector<uint8_t> cut(4 * (size_t)lmax, 0);
         for (int x0 = 0; x0 < T; x0++)
             if ((msk >> x0) & 1ULL) {
-                cut[3 * lmax + (x0 + h) % T] = 1;
-                cut[3 * lmax + ((x0 - h - 1) % T + T) % T] = 1;
+                if (open) {
+                    // slab clipped at the boundaries; the wrap face is always cut
+                    if (x0 + h < T - 1) cut[3 * lmax + x0 + h] = 1;
+                    if (x0 - h - 1 >= 0) cut[3 * lmax + x0 - h - 1] = 1;
+                } else {
+                    cut[3 * lmax + (x0 + h) % T] = 1;
+                    cut[3 * lmax + ((x0 - h - 1) % T + T) % T] = 1;
+                }
             }
+        if (open) cut[3 * lmax + T - 1] = 1;
         disco_domains* dom = nullptr;
         int rd = disco_domains_create(ctx, cut.data(), lmax, &dom);
         if (rd != DISCO_OK) return rd;
@@ -1205,6 +1223,36 @@ int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, c
     if (rl != DISCO_OK) return rl;
     if (status == DISCO_ENOCONV) ctx->err = err;
     return status;
+}
+
+int disco_loops_slab(disco_ctx* ctx, const void* Vin, int nv, const double* w, const int* gammas, int ngamma, int delta,
+                     const disco_solver_params* P, void* L, void* tau_out, disco_solver_stats* agg) {
+    return loops_slab(ctx, Vin, nv, w, gammas, ngamma, delta, false, P, L, tau_out, agg);
+}
+
+int disco_loops_slab_open(disco_ctx* ctx, const void* Vin, int nv, const double* w, const int* gammas, int ngamma,
+                          int delta, const disco_solver_params* P, void* L, void* tau_out, disco_solver_stats* agg) {
+    return loops_slab(ctx, Vin, nv, w, gammas, ngamma, delta, true, P, L, tau_out, agg);
+}
+
+// C^NR spliced by separation: out[dt] = Cc[dt] + dC_k[dt] with k the largest
+// slab width deltas[k] below dt (NaN where none is)
+int disco_nr_splice(const double* Cc, const double* dC, const int* deltas, int ndelta, int T, double* out) {
+    if (!Cc || !dC || !deltas || !out || ndelta < 1 || T < 1) return DISCO_EINVAL;
+    for (int k = 0; k < ndelta; k++)
+        if (deltas[k] < 1) return DISCO_EINVAL;
+    for (int dt = 0; dt < T; dt++) {
+        int best = -1;
+        for (int k = 0; k < ndelta; k++)
+            if (deltas[k] < dt && (best < 0 || deltas[k] > deltas[best])) best = k;
+        if (best < 0) {
+            out[2 * dt] = out[2 * dt + 1] = std::nan("");
+            continue;
+        }
+        out[2 * dt] = Cc[2 * dt] + dC[2 * ((long)best * T + dt)];
+        out[2 * dt + 1] = Cc[2 * dt + 1] + dC[2 * ((long)best * T + dt) + 1];
+    }
+    return DISCO_OK;
 }
 
 // All-to-all perambulators for the connected correlator: sources on every

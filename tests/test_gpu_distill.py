@@ -348,6 +348,62 @@ def test_slab_schedule_loops(disco, delta):
             assert err < 1e-9, (omega, g, err)
 
 
+@pytest.mark.parametrize("delta", [3, 5])
+def test_open_time_slab_schedule_loops(disco, delta):
+    """The paper's open time boundary: slabs clipped at t = 0 and T-1, the wrap
+    face cut in every partition, sets packed by distance on the open line;
+    slab loops against the oracle solving every x0 on its own, and the loops
+    of the full open-boundary operator (domains cutting only the wrap face)
+    against the oracle's; plus C^NR spliced over two widths by the library
+    against the oracle's rule on the same correlators."""
+    dims = (4, 4, 4, 8)
+    kappa, csw = 0.12, 1.0
+    T = dims[3]
+    U = synth.gauge_field(dims, 0.3, 94)
+    A = oracle.clover(U, dims, kappa, csw)
+    Vo, _ = oracle.laplace_eigvecs(oracle.ape_smear(U, dims, 0.5, 2), dims, 3)
+    Lo, _ = oracle.slab_loops(U, A, dims, BC, kappa, Vo, delta, CODES + TCODES, open_time=True)
+    ocut = oracle.open_time_cut(dims)
+    tau_fo = np.stack([oracle.perambulator_tt(U, A, dims, BC, kappa, Vo, t, cut=ocut) for t in range(T)])
+    Lfo = oracle.loops(tau_fo, CODES + TCODES)
+    ctx = _ctx(disco, dims, U, kappa, csw)
+    Vg = ctx.dev(Vo)
+    sets = ctx.slab_sets(delta, open_time=True)
+    assert sorted(sum(([t for t in range(T) if (m >> t) & 1] for m in sets), [])) == list(range(T))
+    for m in sets:   # disjoint on the open line
+        xs = [t for t in range(T) if (m >> t) & 1]
+        assert all(b - a >= delta for a, b in zip(xs, xs[1:]))
+    P = ctx.params(method=disco.BICGSTAB_RU, tol=1e-12, inner_prec=disco.F32, rhs_block=8)
+    L, _, st = ctx.loops_slab(Vg, CODES + TCODES, delta, P, open_time=True)
+    assert ctx.last_solves() == len(sets) * 12
+    wrap = np.zeros((4, max(dims)), dtype=np.uint8)
+    wrap[3, T - 1] = 1   # the open time boundary: only the face between T-1 and 0
+    Lf, _, _ = ctx.loops_distill(Vg, CODES + TCODES, P, ctx.domains(wrap))
+    L, Lf = L.cpu().numpy(), Lf.cpu().numpy()
+    for g in range(2 * NC):
+        for La, Lr in ((L[g], Lo[g]), (Lf[g], Lfo[g])):
+            err = np.abs(La - Lr).max() / np.abs(Lr).max()
+            assert err < 1e-10, (delta, g, err)
+    # C^NR over widths 1 and delta (library splice of the library's correlators vs
+    # the oracle's rule on the oracle's), Gamma = gamma_5
+    L1, _, _ = ctx.loops_slab(Vg, CODES + TCODES, 1, P, open_time=True)
+    L1 = L1.cpu().numpy()
+    L1o, _ = oracle.slab_loops(U, A, dims, BC, kappa, Vo, 1, CODES + TCODES, open_time=True)
+    g = 1
+    dC = [ctx.correlator(*[ctx.dev(v[None]) for v in (Lf[g], Lf[NC + g], Lb[g], Lb[NC + g])])[2].cpu().numpy()
+          for Lb in (L1, L)]
+    dCo = [oracle.correlator(Lfo[g][None], Lfo[NC + g][None], Lbo[g][None], Lbo[NC + g][None])[2]
+           for Lbo in (L1o, Lo)]
+    rng = np.random.default_rng(95)
+    Cc = rng.standard_normal(T) + 1j * rng.standard_normal(T)   # a stand-in connected correlator, both sides
+    got = ctx.nr_splice(Cc, np.stack(dC), [1, delta])
+    ref = oracle.nr_splice(Cc, np.stack(dCo), [1, delta])
+    assert np.array_equal(np.isnan(got), np.isnan(ref)) and np.isnan(got[:2]).all()
+    ok = ~np.isnan(ref)
+    scale = np.abs(ref[ok]).max()
+    assert np.abs(got[ok] - ref[ok]).max() <= 1e-10 * scale
+
+
 @pytest.mark.parametrize("method,blk", [("BICGSTAB_DC", 12), ("BICGSTAB_RU", 5)])
 def test_connected_correlator_and_noise_reduced_estimator(disco, method, blk):
     """All-to-all perambulators on the GPU and the connected contraction (the

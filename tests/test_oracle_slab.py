@@ -72,3 +72,70 @@ def test_profile_weights_closed_form():
     assert abs(w2[0] - np.exp(-4.0)) < 1e-15
     # a very wide profile is standard distillation
     assert np.abs(oracle.profile_weights(np.linspace(0, 2, 7), 1e8) - 1.0).max() < 1e-15
+
+
+def test_open_time_cut_removes_exactly_the_wrap_hops():
+    """The open time boundary as a cut: the dense operator with the face between
+    T-1 and 0 cut equals the dense D with every entry coupling timeslice T-1
+    and timeslice 0 set to zero (and nothing else changed)."""
+    dims = (2, 2, 2, 4)
+    kappa, csw = 0.13, 1.2
+    U = synth.gauge_field(dims, 0.5, 84)
+    A = oracle.clover(U, dims, kappa, csw)
+    D = oracle.dense_dirac(U, A, dims, BC, kappa)
+    Do = oracle.dense_dirac(U, A, dims, BC, kappa, oracle.open_time_cut(dims))
+    Vs, T = 8, dims[3]
+    t_of = np.repeat(np.arange(T), Vs * 12)
+    wrap = ((t_of[:, None] == T - 1) & (t_of[None, :] == 0)) | ((t_of[:, None] == 0) & (t_of[None, :] == T - 1))
+    assert np.abs(D[wrap]).max() > 0.01
+    assert np.array_equal(Do, np.where(wrap, 0, D))
+
+
+@pytest.mark.parametrize("delta", [1, 3])
+def test_open_time_slab_loops_equal_clipped_submatrix_inverse(delta):
+    """With the open time boundary the slab of x0 is clipped at t = 0 and T-1:
+    its loops are those of the inverse of the principal submatrix of the dense
+    open-boundary operator on the clipped slab's sites."""
+    dims = (2, 2, 2, 6)
+    kappa, csw = 0.13, 1.1
+    U = synth.gauge_field(dims, 0.5, 85)
+    A = oracle.clover(U, dims, kappa, csw)
+    Vt, _ = oracle.laplace_eigvecs(oracle.ape_smear(U, dims, 0.5, 1), dims, 2)
+    codes = [oracle.G_1, oracle.G_5, oracle.G_X]
+    L, _ = oracle.slab_loops(U, A, dims, BC, kappa, Vt, delta, codes, tol=1e-14, open_time=True)
+    Do = oracle.dense_dirac(U, A, dims, BC, kappa, oracle.open_time_cut(dims))
+    Vs, Lt = 8, dims[3]
+    h = (delta - 1) // 2
+    for x0 in range(Lt):
+        ts = [t for t in range(x0 - h, x0 + h + 1) if 0 <= t < Lt]
+        sites = np.concatenate([np.arange(t * Vs, (t + 1) * Vs) for t in ts])
+        idx = (sites[:, None] * 12 + np.arange(12)[None, :]).ravel()
+        inv = np.linalg.inv(Do[np.ix_(idx, idx)])
+        k0 = ts.index(x0)
+        blk = inv.reshape(len(ts), Vs, 4, 3, len(ts), Vs, 4, 3)[k0, :, :, :, k0]
+        tau = np.einsum("jxc,xbcyad,iyd->jbia", np.conj(Vt[x0]), blk, Vt[x0])
+        for gi, c in enumerate(codes):
+            ref = oracle.loop_from_tau(tau, oracle.channel_matrix(c))
+            assert abs(L[gi, x0] - ref) <= 1e-11 * max(1.0, abs(ref))
+
+
+def test_nr_splice_takes_the_papers_widths():
+    """The splice rule (the widest width below the separation) reproduces the
+    paper's choice of block size per source-sink distance."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "nr_splice_widths.json")))
+    widths = g["widths"]
+    T = 48
+    Cc = np.zeros(T, dtype=np.complex128)
+    dC = np.array([np.full(T, 1000.0 * w) for w in widths], dtype=np.complex128)   # tags each width
+    out = oracle.nr_splice(Cc, dC, widths)
+    for dt, w in g["width_at_separation"].items():
+        assert out[int(dt)] == 1000.0 * w, (dt, w)
+    assert np.isnan(out[:8]).all()       # no block is narrower than separations up to 7
+    # and it is C^(c) + dC of that width
+    rng = np.random.default_rng(3)
+    Cc = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    dC = rng.standard_normal((4, T)) + 1j * rng.standard_normal((4, T))
+    out = oracle.nr_splice(Cc, dC, widths)
+    assert out[10] == Cc[10] + dC[1][10] and out[30] == Cc[30] + dC[3][30]
