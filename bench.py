@@ -72,6 +72,12 @@ def load_traffic(kernel_tag):
     return ent.get("bytes_per_launch")
 
 
+def traffic_key(kernel_tag, blk, lat, tile):
+    """Key of the committed counter entry for a stencil family, block width,
+    lattice and site-order tile (the counters depend on all four)."""
+    return "%s/n%d/%s/tile%dx%d" % (kernel_tag, blk, lat, tile[0], tile[1])
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
@@ -124,7 +130,8 @@ def stencil_at_batch_shape(d, inner, blk, iters=20):
     fam = d.K_STENCIL_EO_BF16 if inner == d.BF16 else d.K_STENCIL_EO_F32
     tag = "k_dslash_eo<%s>" % ("IOBF" if inner == d.BF16 else "IO32")
     nl, ms, by = ctx.profile_get(fam)
-    roof = stencil_roofline(tag, nl, ms, by, ctx.V // 2, blk, "%s/n%d/24x24x24x48" % (tag, blk))
+    tile = (ctx.get_option(d.OPT_TILE_Y), ctx.get_option(d.OPT_TILE_T))
+    roof = stencil_roofline(tag, nl, ms, by, ctx.V // 2, blk, traffic_key(tag, blk, "24x24x24x48", tile))
     roof["lattice"] = "24x24x24x48"
     del b, ctx
     torch.cuda.empty_cache()
@@ -440,7 +447,9 @@ def main():
     blk = args.rhs_block or tuned
     lat = "x".join(map(str, dims))
     big = args.workload != "prec_16x16x16x32"
-    roof = stencil_roofline(kernel_tag, nl, ms, by, sites, blk, "%s/n%d" % (kernel_tag, blk) + ("/" + lat if big else ""))
+    tile = (ctx.get_option(d.OPT_TILE_Y), ctx.get_option(d.OPT_TILE_T))
+    roof = stencil_roofline(kernel_tag, nl, ms, by, sites, blk, traffic_key(kernel_tag, blk, lat, tile))
+    roof["site_order_tile"] = list(tile)
     comparison = nn_roof = slab = None
     if not args.no_legs:
         comparison, nn_roof = solver_comparison(ctx, d, Vev, inner, args.rhs_block or tuned, T)
@@ -461,6 +470,8 @@ def main():
                                    args.inner, "reliable updates" if args.method == "ru" else "FP64 defect correction"),
                    "lattice": lat, "kappa": pre.kappa, "csw": pre.csw, "nv": nv, "nv_per_step": nvs,
                    "domains": "x".join(map(str, pre.block)), "rhs_block": args.rhs_block or tuned,
+                   "site_order_tile": {"y_rows": ctx.get_option(d.OPT_TILE_Y),
+                                       "timeslices": ctx.get_option(d.OPT_TILE_T)},
                    "autotune_us_per_rhs_iter": {str(k): round(v, 3) for k, v in tune_cost.items()},
                    "inner_storage": args.inner, "hip_graphs": True, "method": args.method,
                    "outer": "f64", "logical_rhs_per_step": rhs // max(args.steps, 1),

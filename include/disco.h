@@ -218,9 +218,22 @@ enum {
                            * (D = A - kappa H; half-lattice vectors) when every extent is even,
                            * with the source A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o) and the odd
                            * sites reconstructed as A_oo^-1 (r_o + kappa H_oe e_e); the FP64
-                           * outer residual stays that of the full operator.  0: full operator */
+                           * outer residual stays that of the full operator.  0: full operator */,
+    DISCO_OPT_TILE_Y = 4, /* the stencil's site order: y rows per tile (a divisor of Ly; 0 = the
+                           * default rule); each XCD of the chip takes a slab of Lt/8
+                           * timeslices (when 8 divides Lt) and visits it x fastest, then the
+                           * y rows of a tile, the timeslices of a tile, z, the y tiles, the t
+                           * tiles, so that neighbours stay in its L2.  Setting it rewrites the
+                           * order: each site's arithmetic is unchanged, so operator outputs
+                           * are the same bit for bit; the solvers' fused sums group sites by
+                           * this order and change by rounding */
+    DISCO_OPT_TILE_T = 5  /* timeslices per tile inside the slab (a divisor of it; 0 = the whole
+                           * slab).  disco_autotune sets both */
 };
 int disco_set_option(disco_ctx* ctx, int option, int value);
+/* The current value of an option; for the tile options, the extents the site
+ * order was built with. */
+int disco_get_option(const disco_ctx* ctx, int option, int* value);
 
 /* ---------------------------------------------------------------- solver */
 typedef struct {
@@ -425,7 +438,11 @@ int disco_effective_mass(const double* C, int n, double* meff);
  * rhs_block = 0 (BICGSTAB_DC uses at most 32 of it: its fixed blocks wait for
  * their slowest member, while BICGSTAB_RU refills finished lanes).  best (host) receives it; cost_us (host, 4 entries, may be
  * NULL) the measured microseconds per right-hand side and iteration, 0 for a
- * block not tried.  A block is tried only if one spinor plane of it
+ * block not tried.  Then, at the chosen block, it times the tile of the
+ * stencil's site order (DISCO_OPT_TILE_Y, DISCO_OPT_TILE_T: y rows 1, 2, 3, 4,
+ * 6, 8 that divide Ly, and the whole XCD slab of timeslices or half of it, up
+ * to 1024 sites per z step) and keeps the fastest, the current tile included;
+ * disco_get_option reads the result.  A block is tried only if one spinor plane of it
  * (V * block * 16 bytes at every precision) stays below 4 GiB, the limit of
  * the stencil's 32-bit offsets; solves clamp rhs_block to the same limit. */
 int disco_autotune(disco_ctx* ctx, const disco_domains* dom, int inner_prec, int* best, double* cost_us);

@@ -26,7 +26,7 @@ K_STENCIL = 0
 K_NN = 2
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
 K_MFMA = 1
-OPT_GRAPHS, OPT_STAGE, OPT_EO = 1, 2, 3
+OPT_GRAPHS, OPT_STAGE, OPT_EO, OPT_TILE_Y, OPT_TILE_T = 1, 2, 3, 4, 5
 K_STENCIL_EO_F64, K_STENCIL_EO_F32, K_STENCIL_EO_BF16 = 13, 14, 15
 
 
@@ -98,6 +98,7 @@ _SIGS.update({
                                 ctypes.POINTER(SolverStats)], I),
     "disco_profile_stride": ([P, I], I),
     "disco_set_option": ([P, I, I], I),
+    "disco_get_option": ([P, I, ctypes.POINTER(I)], I),
     "disco_autotune": ([P, P, I, ctypes.POINTER(I), P], I),
     "disco_correlator": ([P, P, P, P, P, I, I, P, I, I, P, P, P, P], I),
     "disco_slab_sets": ([I, I, ctypes.POINTER(I), P], I),
@@ -528,6 +529,11 @@ class Context:
 
     def set_option(self, option, value):
         self._chk(lib().disco_set_option(self.h, int(option), int(value)))
+
+    def get_option(self, option):
+        v = I()
+        self._chk(lib().disco_get_option(self.h, int(option), ctypes.byref(v)))
+        return v.value
 
     def autotune(self, inner_prec=F32, dom: Domains | None = None):
         best = ctypes.c_int(0)

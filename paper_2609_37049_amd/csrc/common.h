@@ -100,6 +100,10 @@ struct disco_ctx {
     // the same order restricted to the sites of one parity (x+y+z+t even / odd);
     // a site s of either parity has index s/2 in a half-lattice vector
     int2* d_trav_eo[2] = {nullptr, nullptr};
+    // tile of the site order: y rows and timeslices (0 = the default rule), and
+    // the tile the tables were last built with
+    int tile_y = 0, tile_t = 0;
+    int tile_used[2] = {0, 0};
 
     // named, grow-only device workspaces
     std::map<std::string, std::pair<void*, size_t>> ws;

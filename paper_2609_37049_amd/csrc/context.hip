@@ -528,10 +528,35 @@ int disco_set_option(disco_ctx* ctx, int option, int value) {
         } else if (option == DISCO_OPT_EO) {
             REQUIRE(value == 0 || value == 1, DISCO_EINVAL, "even-odd option is 0 or 1");
             ctx->opt_eo = value;
+        } else if (option == DISCO_OPT_TILE_Y || option == DISCO_OPT_TILE_T) {
+            REQUIRE(value >= 0 && value <= 255, DISCO_EINVAL, "tile extent %d", value);
+            activate(ctx);
+            int& f = option == DISCO_OPT_TILE_Y ? ctx->tile_y : ctx->tile_t;
+            const int old = f;
+            f = value;
+            try {
+                disco::build_traversal(ctx);
+            } catch (...) {
+                f = old;
+                throw;
+            }
         } else {
             disco_throw(DISCO_EINVAL, "unknown option %d", option);
         }
     });
+}
+
+int disco_get_option(const disco_ctx* ctx, int option, int* value) {
+    if (!ctx || !value) return DISCO_EINVAL;
+    switch (option) {
+        case DISCO_OPT_GRAPHS: *value = ctx->opt_graphs; break;
+        case DISCO_OPT_STAGE: *value = ctx->opt_stage; break;
+        case DISCO_OPT_EO: *value = ctx->opt_eo; break;
+        case DISCO_OPT_TILE_Y: *value = ctx->tile_used[0]; break;
+        case DISCO_OPT_TILE_T: *value = ctx->tile_used[1]; break;
+        default: return DISCO_EINVAL;
+    }
+    return DISCO_OK;
 }
 
 int disco_profile_enable(disco_ctx* ctx, int on) {

@@ -70,8 +70,9 @@ __device__ __forceinline__ u2v bld8(brsrc r, unsigned voff, unsigned soff) {
     return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
 }
 
-// Read-only views handed to the stencil: base pointer, bytes, and whether the
-// buffer path applies (nbytes < 4 GiB).
+// Read-only views handed to the stencil: base pointer, bytes a descriptor
+// covers (the whole block; one plane for FP64), and whether the buffer path
+// applies (those bytes below 4 GiB).
 struct RoView {
     const void* p;
     unsigned nbytes;
@@ -101,15 +102,17 @@ struct IO64 {
 #pragma unroll
         for (int k = 0; k < 12; k++) st_at<NT>(b, k * ps, off, make_double2(p[k].re, p[k].im));
     }
+    // FP64 blocks reach 4 GiB long before one plane does (12 planes of
+    // V n 16 bytes): one descriptor per plane, b.nbytes = the plane's bytes
     template <bool BUF>
     __device__ __forceinline__ static void loadv(const RoView& b, long V, int n, int r, int s, cx<T> p[12]) {
         if constexpr (BUF) {
-            const brsrc rs = make_rsrc(b.p, b.nbytes);
             const unsigned off = ((unsigned)s * (unsigned)n + (unsigned)r) * 16u;
-            const unsigned ps = (unsigned)V * (unsigned)n * 16u;
+            const size_t ps = (size_t)V * n * 16;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
-                u4v v = bld16(rs, off, k * ps);
+                const brsrc rs = make_rsrc((const char*)b.p + k * ps, b.nbytes);
+                u4v v = bld16(rs, off, 0u);
                 p[k] = mk(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2]));
             }
         } else {

@@ -529,14 +529,17 @@ int plane_rhs_limit(const disco_ctx* ctx) {
 
 // Site order of the stencil.  Each XCD (8 contiguous ranges of the order)
 // takes one slab of Lt/8 timeslices when Lt is a multiple of 8.  Inside a slab
-// the order is x fastest, then y within a tile of yt rows, then t within the
-// slab, then z, then the y tiles: hops in t and z then land a few hundred
-// sites away in the visiting order (instead of a whole timeslice), so the
-// neighbours of the sites in flight are still in that XCD's L2.  yt is the
-// largest divisor of Ly with Lx * yt * (Lt/8) <= 320 sites per z step, but at
-// least 2 when Ly is even: single-row tiles send every y hop across a tile
-// (4, 2 and 2 rows at 16^3x32, 24^3x48 and 32^3x64).
-// DISCO_TRAVERSAL = natural restores lexicographic order.
+// the order is x fastest, then y within a tile of yt rows, then t within a
+// tile of tt timeslices, then z, then the y tiles, then the t tiles: hops in t
+// and z then land a few hundred sites away in the visiting order (instead of a
+// whole timeslice), so the neighbours of the sites in flight are still in that
+// XCD's L2.  By default tt is the whole slab and yt the largest divisor of Ly
+// with Lx * yt * (Lt/8) <= 320 sites per z step, but at least 2 when Ly is
+// even: single-row tiles send every y hop across a tile (4, 2 and 2 rows at
+// 16^3x32, 24^3x48 and 32^3x64).  ctx->tile_y and ctx->tile_t (divisors of Ly
+// and of the slab; 0 = the default) override the tile; the autotuner sets
+// them.  DISCO_TRAVERSAL = natural restores lexicographic order.  The tables
+// are rewritten in place, so graphs captured with them stay valid.
 void build_traversal(disco_ctx* ctx) {
     const int Lx = ctx->dims[0], Ly = ctx->dims[1], Lz = ctx->dims[2], Lt = ctx->dims[3];
     const long V = ctx->V;
@@ -560,15 +563,24 @@ void build_traversal(disco_ctx* ctx) {
         for (int c = 1; c <= Ly; c++)
             if (Ly % c == 0 && (long)Lx * c * tc <= 320) yt = c;
         if (yt == 1 && Ly % 2 == 0) yt = 2;
+        if (ctx->tile_y > 0) yt = ctx->tile_y;
+        const int tt = ctx->tile_t > 0 ? ctx->tile_t : tc;
+        REQUIRE(Ly % yt == 0 && tc % tt == 0, DISCO_EINVAL, "tile %d x %d does not divide Ly = %d and the slab of %d",
+                yt, tt, Ly, tc);
         for (int ch = 0; ch < nch; ch++)
-            for (int yb = 0; yb < Ly / yt; yb++)
-                for (int z = 0; z < Lz; z++)
-                    for (int tl = 0; tl < tc; tl++)
-                        for (int yi = 0; yi < yt; yi++)
-                            for (int x = 0; x < Lx; x++) put(g++, x, yb * yt + yi, z, ch * tc + tl);
+            for (int tb = 0; tb < tc / tt; tb++)
+                for (int yb = 0; yb < Ly / yt; yb++)
+                    for (int z = 0; z < Lz; z++)
+                        for (int tl = 0; tl < tt; tl++)
+                            for (int yi = 0; yi < yt; yi++)
+                                for (int x = 0; x < Lx; x++) put(g++, x, yb * yt + yi, z, ch * tc + tb * tt + tl);
+        ctx->tile_used[0] = yt;
+        ctx->tile_used[1] = tt;
     }
     ctx->trav_kind = natural ? 0 : 1;
-    HIPCHK(hipMalloc(&ctx->d_trav, sizeof(int2) * V));
+    // tables in flight on the stream must not change under a kernel
+    if (ctx->d_trav) HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!ctx->d_trav) HIPCHK(hipMalloc(&ctx->d_trav, sizeof(int2) * V));
     HIPCHK(hipMemcpy(ctx->d_trav, tr.data(), sizeof(int2) * V, hipMemcpyHostToDevice));
     if (V % 2 == 0) {
         std::vector<int2> par[2];
@@ -577,7 +589,8 @@ void build_traversal(disco_ctx* ctx) {
             par[((c & 0xff) + ((c >> 8) & 0xff) + ((c >> 16) & 0xff) + ((c >> 24) & 0xff)) & 1].push_back(tr[k]);
         }
         for (int p = 0; p < 2; p++) {
-            HIPCHK(hipMalloc(&ctx->d_trav_eo[p], sizeof(int2) * std::max<size_t>(1, par[p].size())));
+            if (!ctx->d_trav_eo[p])
+                HIPCHK(hipMalloc(&ctx->d_trav_eo[p], sizeof(int2) * std::max<size_t>(1, par[p].size())));
             HIPCHK(hipMemcpy(ctx->d_trav_eo[p], par[p].data(), sizeof(int2) * par[p].size(), hipMemcpyHostToDevice));
         }
     }
@@ -605,7 +618,9 @@ void stencil_launch(disco_ctx* ctx, const StencilCall& c) {
     REQUIRE(!eo || (eo_supported(ctx) && c.eo_target <= 1 && !c.dagger && !(c.epi & EPI_RESID)), DISCO_EINVAL,
             "even-odd stencil needs even extents, no dagger and no residual epilogue");
     StencilArgs a;
-    const size_t blk = native_bytes(ctx, c.prec, c.nrhs) / (eo ? 2 : 1);
+    // bytes one buffer descriptor covers: the whole block, or one plane for
+    // FP64 (whose twelve planes pass 4 GiB first)
+    const size_t blk = native_bytes(ctx, c.prec, c.nrhs) / (eo ? 2 : 1) / (c.prec == DISCO_F64 ? 12 : 1);
     const int buf = blk < (1ULL << 32) ? 1 : 0;
     a.in = RoView{c.in, (unsigned)blk, buf};
     a.out = c.out;

@@ -2,6 +2,7 @@
 
     python paper_2609_37049_amd/profile_stencil.py [--dims 16x16x16x32] [--nrhs 32]
                                                    [--prec bf16|f32|f64] [--reps 10] [--solver-iters 20]
+                                                   [--tile Y,T]
 
 Launches the Wilson-clover stencil on native blocks of random spinors in the
 launch configuration the solver uses (nrhs right-hand sides per launch, LDS
@@ -9,7 +10,8 @@ staging as the library chooses).  Then, with --solver-iters K > 0, runs K
 inner iterations of the mixed-precision BiCGStab (reliable updates) on nrhs
 random right-hand sides with HIP graphs off, so that every stencil launch the solver makes
 (with its dot-product epilogues) is an ordinary dispatch a counter run can
-see.  Last comes a plain 256 MiB device-to-device copy whose byte counts
+see.  --tile sets the tile of the site order (y rows, timeslices; the
+autotuner's choice in a benchmark run) instead of the default rule.  Last comes a plain 256 MiB device-to-device copy whose byte counts
 calibrate the FETCH_SIZE / WRITE_SIZE counters.  Prints the algorithmic
 bytes per stencil launch.
 """
@@ -34,6 +36,7 @@ def main():
     ap.add_argument("--prec", default="bf16", choices=["bf16", "f32", "f64"])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--solver-iters", type=int, default=20)
+    ap.add_argument("--tile", default="")
     args = ap.parse_args()
     dims = tuple(int(v) for v in args.dims.split("x"))
     prec = {"f64": d.F64, "f32": d.F32, "bf16": d.BF16}[args.prec]
@@ -42,6 +45,10 @@ def main():
     ctx = d.Context(dims, (1, 1, 1, -1))
     ctx.gauge_set(U)
     ctx.clover_setup(0.125, 1.5)
+    if args.tile:
+        ty, tt = (int(v) for v in args.tile.split(","))
+        ctx.set_option(d.OPT_TILE_Y, ty)
+        ctx.set_option(d.OPT_TILE_T, tt)
     nb = ctx.native_bytes(prec, n)
     x = (torch.rand(nb // 4, device="cuda") - 0.5).view(torch.uint8)
     if prec == d.BF16:
@@ -71,8 +78,9 @@ def main():
     V = ctx.V
     alg_read = V * (n * 24 * sp + 144 * sg)
     alg_write = V * n * 24 * sp
-    print("stencil %s %s nrhs %d: algorithmic read %d B, write %d B per launch; copy %d B read + %d B write"
-          % (args.dims, args.prec, n, alg_read, alg_write, src.numel() * 4, src.numel() * 4), flush=True)
+    print("stencil %s %s nrhs %d tile %d,%d: algorithmic read %d B, write %d B per launch; copy %d B read + %d B write"
+          % (args.dims, args.prec, n, ctx.get_option(d.OPT_TILE_Y), ctx.get_option(d.OPT_TILE_T), alg_read, alg_write,
+             src.numel() * 4, src.numel() * 4), flush=True)
 
 
 if __name__ == "__main__":

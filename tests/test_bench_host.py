@@ -32,12 +32,25 @@ def test_roofline_arithmetic():
     assert r["traffic"] is None and r["traffic_gbps"] is None
 
 
+def _tiles(L_x, slab):
+    """The site-order tiles the autotuner may pick (its candidates and the default)."""
+    out = set()
+    for y in (1, 2, 3, 4, 6, 8):
+        for t in (slab, slab // 2):
+            if L_x % y == 0 and t >= 1 and slab % t == 0 and y * t * L_x <= 1024:
+                out.add((y, t))
+    return out
+
+
 def test_committed_counters_belong_to_the_current_stencil():
     """profiles/stencil_traffic.json holds the calibrated FETCH_SIZE + WRITE_SIZE
-    bytes of the dominant stencil; they must have been taken on the stencil
-    sources as they are now (else the bench reports null traffic)."""
+    bytes of the dominant stencil for every tile the autotuner can pick at the
+    two benchmark lattices; they must have been taken on the stencil sources as
+    they are now (else the bench reports null traffic)."""
     d = json.load(open(os.path.join(ROOT, "profiles", "stencil_traffic.json")))
-    for key in ("k_dslash_eo<IOBF>/n64", "k_dslash_eo<IOBF>/n64/24x24x24x48"):
+    keys = [bench.traffic_key("k_dslash_eo<IOBF>", 64, "24x24x24x48", t) for t in _tiles(24, 6) | {(2, 6)}]
+    keys += [bench.traffic_key("k_dslash_eo<IOBF>", 64, "16x16x16x32", t) for t in _tiles(16, 4) | {(4, 4)}]
+    for key in keys:
         assert d[key]["source_hash"] == bench.stencil_hash(), key
         t = bench.load_traffic(key)
         assert t == d[key]["bytes_per_launch"]
@@ -47,6 +60,7 @@ def test_committed_counters_belong_to_the_current_stencil():
 
 def test_traffic_is_null_when_the_sources_change(monkeypatch):
     monkeypatch.setattr(bench, "stencil_hash", lambda: "0000000000000000")
-    assert bench.load_traffic("k_dslash_eo<IOBF>/n64") is None
-    r = bench.stencil_roofline("k_dslash_eo<IOBF>", 1, 1.0, 1e9, 65536, 64, "k_dslash_eo<IOBF>/n64")
+    key = bench.traffic_key("k_dslash_eo<IOBF>", 64, "24x24x24x48", (2, 6))
+    assert bench.load_traffic(key) is None
+    r = bench.stencil_roofline("k_dslash_eo<IOBF>", 1, 1.0, 1e9, 65536, 64, key)
     assert r["traffic"] is None and r["traffic_gbps"] is None

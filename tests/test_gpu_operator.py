@@ -209,3 +209,38 @@ def test_native_apply_plane_offset_limit(disco):
     ctx.dirac_apply_native(None, disco.BF16, x[:nb], y[:nb], n)
     torch.cuda.synchronize()
     assert int(y[:nb].count_nonzero()) == 0
+
+
+def test_site_order_tiles_keep_the_operator_bit_for_bit(disco):
+    """The tile of the stencil's site order (set directly, or by the autotuner)
+    changes only which sites a launch visits together: D, D_Lambda and the
+    even-odd pieces give the same bits under every tile, and an invalid tile is
+    refused without changing the current one."""
+    dims = (8, 8, 8, 16)
+    ctx, U, A = _setup(disco, dims, 0.4, 51, 0.124, 1.2)
+    cut = synth.tiling_cuts(dims, (4, 4, 4, 8))
+    dom = ctx.domains(cut)
+    psi = ctx.dev(synth.random_spinor(ctx.V, 16, 52))
+    aux = ctx.dev(synth.random_spinor(ctx.V, 16, 53))
+
+    def outputs():
+        return [ctx.dirac_apply(psi, disco.BF16).cpu().numpy(),
+                ctx.dirac_block_apply(dom, psi, disco.F32).cpu().numpy(),
+                ctx.dirac_eo_apply(psi, 0, 1.0, 0.0, -0.124 ** 2, disco.BF16, dom, aux)[0].cpu().numpy()]
+    ref = outputs()
+    assert (ctx.get_option(disco.OPT_TILE_Y), ctx.get_option(disco.OPT_TILE_T)) == (8, 2)
+    for yt, tt in ((1, 2), (2, 1), (4, 2), (8, 1)):
+        ctx.set_option(disco.OPT_TILE_Y, yt)
+        ctx.set_option(disco.OPT_TILE_T, tt)
+        assert (ctx.get_option(disco.OPT_TILE_Y), ctx.get_option(disco.OPT_TILE_T)) == (yt, tt)
+        for a, b in zip(outputs(), ref):
+            assert np.array_equal(a, b), (yt, tt)
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.set_option(disco.OPT_TILE_Y, 3)          # 3 does not divide Ly = 8
+    assert e.value.code == disco.EINVAL
+    assert ctx.get_option(disco.OPT_TILE_Y) == 8
+    best, cost = ctx.autotune(disco.BF16)
+    yt, tt = ctx.get_option(disco.OPT_TILE_Y), ctx.get_option(disco.OPT_TILE_T)
+    assert dims[1] % yt == 0 and 2 % tt == 0
+    for a, b in zip(outputs(), ref):
+        assert np.array_equal(a, b)
