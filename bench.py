@@ -1,7 +1,8 @@
 """Benchmark of the hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--method ru|dc]
-                    [--workload batch_24x24x24x48|prec_16x16x16x32] [--nv-per-step N]
+                    [--workload batch_24x24x24x48|prec_16x16x16x32|prod_32x32x32x64|learned_24x24x24x48]
+                    [--nv-per-step N] [--nn-pairs P] [--nn-steps S]
                     [--no-cpu-baseline] [--no-legs]
 
 Workload (default): the batching configuration, a 24^3 x 48 lattice
@@ -13,6 +14,10 @@ the even-odd Schur complement and FP64 reliable updates (--method dc: inside
 FP64 defect correction), 64 right-hand sides per launch fed from one queue.
 --workload prec_16x16x16x32 runs the same step on the 16^3 x 32 precision
 shape (kappa = 0.125, csw = 1.5, Nv = 32, domains 4^3 x 8).
+--workload prod_32x32x32x64 times a stated subset of the production shape
+(32^3 x 64, four ensembles; see production_subset), and --workload
+learned_24x24x24x48 the learned preconditioner's configuration (see
+learned_form).
 
 One step is one batch of the whole hot path: the four timeslices of one
 multi-site packing set (one timeslice per temporal layer of the partition)
@@ -301,6 +306,205 @@ def cpu_baseline(pre, nrhs=2):
                          " and ".join(str(a) for a in range(nrhs)))}
 
 
+def production_subset(args, d, torch, synth):
+    """The production shape, 32^3 x 64 (eps = 0.2, 10 APE steps, kappa = 0.127,
+    csw = 1.7, Nv = 128), over four seeded ensembles (seeds 500-503), as a stated
+    subset: per ensemble one packing set (timeslices 0, 16, 32, 48: one per
+    temporal layer of the 8^3 x 16 domains, two per layer of the 16^3 x 32
+    domains) and the first nv_sub of the 128 eigenvectors (computed on those
+    four timeslices only) -- full-operator solves, packed D_Lambda solves on both
+    domain sizes, loops of gamma_5, gamma_1..3 and 1 with their Gamma-tilde, and
+    the full / factorised / subtracted correlators over the four ensembles at
+    the separations the packing set covers (0, 16, 32, 48; per-timeslice VEV)."""
+    pre = synth.PRESETS["prod_32x32x32x64"]
+    dims, T, nv = pre.dims, pre.dims[3], pre.nv
+    nvs = args.nv_per_step or 4
+    tsel = [0, 16, 32, 48]
+    tmask = sum(1 << t for t in tsel)
+    codes = [d.G_5, d.G_X, d.G_Y, d.G_Z, d.G_1]
+    nc = len(codes)
+    loop_codes = codes + [c | d.G_TILDE for c in codes]
+    inner = d.BF16 if args.inner == "bf16" else d.F32
+    ctx = d.Context(dims, pre.bc, 0)
+    doms = {"8x8x8x16": ctx.domains(synth.tiling_cuts(dims, (8, 8, 8, 16))),
+            "16x16x16x32": ctx.domains(synth.tiling_cuts(dims, (16, 16, 16, 32)))}
+    P = ctx.params(method=d.BICGSTAB_RU, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block)
+    dev = "cuda:0"
+    Vfull = torch.zeros((T, nvs, ctx.Vs, 3), dtype=torch.complex128, device=dev)
+    L = {k: torch.zeros((len(loop_codes), 4, T), dtype=torch.complex128, device=dev) for k in ["full"] + list(doms)}
+    solve_s = setup_s = 0.0
+    logical = {k: 0 for k in L}
+    packed = {k: 0 for k in L}
+    secs = {k: 0.0 for k in L}
+    worst = 0.0
+    tuned = None
+    for c, seed in enumerate(range(500, 504)):
+        t0 = time.perf_counter()
+        U = synth.gauge_field(dims, pre.eps, seed)
+        t_gen = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.gauge_set(U)
+        del U
+        ctx.clover_setup(pre.kappa, pre.csw)
+        ctx.ape_smear(pre.ape_steps, pre.ape_alpha)
+        Vs_, lam = ctx.laplace_eigvecs_slices(nv, tsel, 1e-11)
+        for k, t in enumerate(tsel):
+            Vfull[t].copy_(Vs_[k, :nvs])
+        del Vs_
+        if tuned is None:
+            tuned, _ = ctx.autotune(inner)
+        torch.cuda.synchronize()
+        setup_s += time.perf_counter() - t0
+        print("ensemble %d: links %.1f s, set-up %.1f s (gap lambda_%d - lambda_%d = %.3g at t=0)"
+              % (seed, t_gen, time.perf_counter() - t0, nv, nv - 1, lam[0, -1] - lam[0, -2]), file=sys.stderr,
+              flush=True)
+        for k, dom in [("full", None)] + list(doms.items()):
+            tau = torch.zeros((T, nvs, 4, nvs, 4), dtype=torch.complex128, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a = ctx.perambulators_tt(Vfull, tmask, P, tau, dom)
+            n_solves = ctx.last_solves()
+            Lc = ctx.loops(tau, loop_codes)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            L[k][:, c].copy_(Lc)
+            secs[k] += dt
+            solve_s += dt
+            logical[k] += 4 * nvs * len(tsel)
+            packed[k] += n_solves
+            worst = max(worst, a.true_rel_residual)
+            print("  %s: %d solves in %.1f s, worst residual %.2e" % (k, n_solves, dt, a.true_rel_residual),
+                  file=sys.stderr, flush=True)
+    # correlators over the four ensembles at the covered separations
+    corr = {}
+    sep = [0, 16, 32, 48]
+    for k in doms:
+        for g, code in enumerate(codes):
+            C, Cf, dC, _ = ctx.correlator(L["full"][g], L["full"][nc + g], L[k][g], L[k][nc + g], y0s=tsel,
+                                          vev_mode=0)
+            C, dC = C.cpu().numpy(), dC.cpu().numpy()
+            name = {d.G_5: "g5", d.G_X: "g1", d.G_Y: "g2", d.G_Z: "g3", d.G_1: "1"}[code]
+            corr.setdefault(name, {})["C_full"] = [[round(C[t].real, 6), round(C[t].imag, 6)] for t in sep]
+            corr[name]["dC_" + k] = [[round(dC[t].real, 6), round(dC[t].imag, 6)] for t in sep]
+    # the stencil of the last ensemble's full-operator solves, event-timed
+    ctx.profile_reset()
+    ctx.profile_stride(1)
+    ctx.profile_enable(True)
+    tau = torch.zeros((T, nvs, 4, nvs, 4), dtype=torch.complex128, device=dev)
+    ctx.perambulators_tt(Vfull, 1 << tsel[0], P, tau)
+    ctx.profile_enable(False)
+    fam = d.K_STENCIL_EO_BF16 if inner == d.BF16 else d.K_STENCIL_EO_F32
+    tag = "k_dslash_eo<%s>" % ("IOBF" if inner == d.BF16 else "IO32")
+    nl, ms, by = ctx.profile_get(fam)
+    blk = args.rhs_block or tuned
+    tile = (ctx.get_option(d.OPT_TILE_Y), ctx.get_option(d.OPT_TILE_T))
+    roof = stencil_roofline(tag, nl, ms, by, ctx.V // 2, blk, traffic_key(tag, blk, "32x32x32x64", tile))
+    roof["site_order_tile"] = list(tile)
+    rhs = sum(logical.values())
+    out = {"metric": METRIC, "value": round(rhs / solve_s, 2), "unit": "RHS/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "32x32x32x64 Wilson-clover kappa=%g csw=%g, 4 ensembles (seeds 500-503), Nv=%d "
+                                  "of which the first %d per source, packing set t=0,16,32,48, domains 8^3x16 and "
+                                  "16^3x32, BiCGStab %s-storage/FP32 inner with FP64 reliable updates to 1e-10"
+                                  % (pre.kappa, pre.csw, nv, nvs, args.inner),
+                      "lattice": "32x32x32x64", "ensembles": 4, "nv": nv, "nv_used": nvs, "timeslices": tsel,
+                      "rhs_block": blk, "site_order_tile": list(tile)},
+           "rates": {k: {"logical_rhs": logical[k], "solves": packed[k], "seconds": round(secs[k], 2),
+                         "logical_rhs_per_s": round(logical[k] / secs[k], 2)} for k in L},
+           "roofline": roof, "correlators_at_separations": {"separations": sep, "channels": corr},
+           "worst_true_rel_residual": worst, "setup_s": round(setup_s, 1),
+           "subset": "one packing set of 4 timeslices and %d of the 128 eigenvectors per ensemble: %d of the 4 x "
+                     "65536 logical RHS of the full run" % (nvs, rhs)}
+    print(json.dumps(out), flush=True)
+
+
+def learned_form(args, d, torch, synth):
+    """The learned configuration at 24^3 x 48 (kappa = 0.126, csw = 1.6), as a
+    stated subset of its training: the network is trained on (residual, error)
+    pairs the solver generates, streamed from the eight training ensembles
+    (seeds 100-107; each ensemble's pairs are generated, trained on and
+    discarded before the next), then judged on a held-out ensemble (seed 200):
+    FGMRES(16) with the trained network and without the FP64 fallback, the
+    same with the untrained network (the gain), unpreconditioned FP64
+    BiCGStab, plain FP64 CGNR and the mixed-precision batched solver, all to
+    true relative residual 1e-10 on the same 8 sources (Gaussian colour vectors
+    on timeslice 0, two vectors x four spins)."""
+    pre = synth.PRESETS["batch_24x24x24x48"]
+    dims = pre.dims
+    npairs, steps = args.nn_pairs, args.nn_steps
+    ctx = d.Context(dims, pre.bc, 0)
+    ctx.gauge_set(synth.gauge_field(dims, pre.eps, 100))
+    ctx.clover_setup(pre.kappa, pre.csw)
+    net = d.Net(ctx, 16, 7)
+    untrained = d.Net(ctx, 16, 7)
+    train = []
+    t0 = time.perf_counter()
+    for seed in range(100, 108):
+        if seed != 100:
+            ctx.gauge_set(synth.gauge_field(dims, pre.eps, seed))
+            ctx.clover_setup(pre.kappa, pre.csw)
+            net.refresh()
+        ts = net.train(npairs, snap_iters=(0, 16, 64, 192), batch=4, steps=steps, lr=2e-3, seed=seed)
+        train.append({"seed": seed, "pairs": ts.pairs, "steps": ts.steps, "loss_first": round(ts.first_loss, 4),
+                      "loss_final": round(ts.final_loss, 4), "gen_s": round(ts.gen_seconds, 1),
+                      "train_s": round(ts.train_seconds, 1)})
+        print("trained on seed %d: loss %.3f -> %.3f" % (seed, ts.first_loss, ts.final_loss), file=sys.stderr,
+              flush=True)
+    train_s = time.perf_counter() - t0
+    ctx.gauge_set(synth.gauge_field(dims, pre.eps, 200))
+    ctx.clover_setup(pre.kappa, pre.csw)
+    net.refresh()
+    untrained.refresh()
+    Vn = synth.random_colour_vectors(dims[3], 2, ctx.Vs, 201)
+    b = torch.zeros((8, ctx.V, 4, 3), dtype=torch.complex128, device="cuda:0")
+    for i in range(2):
+        for a in range(4):
+            b[4 * i + a, :ctx.Vs, a, :] = torch.from_numpy(Vn[0, i]).to("cuda:0")
+    out = {}
+
+    def run(name, P, nb, allow=False):
+        bb = b[:nb].contiguous()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = ctx.solve_multi_rhs(bb, P, allow_noconv=allow)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[name] = {"rhs_per_s": round(nb / dt, 3), "rhs": nb, "iters": max(s.iters for s in st),
+                     "converged": all(s.converged for s in st), "fallback_used": max(s.fallback_used for s in st),
+                     "worst_true_rel_residual": max(s.true_rel_residual for s in st)}
+        print("%s: %.3f RHS/s, %d iterations" % (name, nb / dt, out[name]["iters"]), file=sys.stderr, flush=True)
+
+    ctx.profile_reset()
+    ctx.profile_stride(1)
+    ctx.profile_enable(True)
+    run("fgmres16_trained_network_no_fallback",
+        ctx.params(method=d.FGMRES_NN, tol=1e-10, net=net, restart=16, rhs_block=8, fallback=0, max_iter=1500), 8,
+        True)
+    ctx.profile_enable(False)
+    nl, ms, fl = ctx.profile_get(d.K_NN)
+    tf = fl / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    run("fgmres16_untrained_network_no_fallback",
+        ctx.params(method=d.FGMRES_NN, tol=1e-10, net=untrained, restart=16, rhs_block=8, fallback=0, max_iter=800),
+        8, True)
+    ctx.set_option(d.OPT_EO, 0)
+    run("bicgstab_f64_unpreconditioned", ctx.params(method=d.BICGSTAB_DC, tol=1e-10, inner_prec=d.F64,
+                                                    rhs_block=1), 2)
+    ctx.set_option(d.OPT_EO, 1)
+    run("cgnr_f64_plain", ctx.params(method=d.CGNR_F64, tol=1e-10, rhs_block=1), 2)
+    run("mixed_batched_reliable_updates_no_network", ctx.params(method=d.BICGSTAB_RU, tol=1e-10, inner_prec=d.BF16,
+                                                                 rhs_block=8), 8)
+    res = {"metric": "learned preconditioner at 24x24x24x48: RHS/s and iterations at true rel. residual 1e-10",
+           "workload": "24x24x24x48 kappa=%g csw=%g; network 16 channels, 3^4 parallel-transport kernels; trained on "
+                       "%d pairs per ensemble streamed from seeds 100-107 (%d in all), %d Adam steps each; judged on "
+                       "seed 200" % (pre.kappa, pre.csw, npairs, 8 * npairs, steps),
+           "training": train, "training_s": round(train_s, 1), "solvers": out,
+           "nn_roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "launches": nl,
+                           "avg_launch_ms": round(ms / max(nl, 1), 3)}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
@@ -316,7 +520,10 @@ def main():
                     help="skip the solver comparison and the region-schedule legs after the timed steps")
     ap.add_argument("--nv-per-step", type=int, default=0,
                     help="eigenvectors per step (a divisor of Nv; default Nv/4 at 24^3x48, Nv at 16^3x32)")
-    ap.add_argument("--workload", choices=["batch_24x24x24x48", "prec_16x16x16x32"], default="batch_24x24x24x48")
+    ap.add_argument("--workload", choices=["batch_24x24x24x48", "prec_16x16x16x32", "prod_32x32x32x64",
+                                           "learned_24x24x24x48"], default="batch_24x24x24x48")
+    ap.add_argument("--nn-pairs", type=int, default=64, help="learned workload: pairs per training ensemble")
+    ap.add_argument("--nn-steps", type=int, default=150, help="learned workload: Adam steps per training ensemble")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solves of different right-hand sides are independent, so "
@@ -328,6 +535,13 @@ def main():
     import synth
     import paper_2609_37049_amd as d
 
+    torch.cuda.set_device(0)
+    if args.workload == "prod_32x32x32x64":
+        production_subset(args, d, torch, synth)
+        return
+    if args.workload == "learned_24x24x24x48":
+        learned_form(args, d, torch, synth)
+        return
     pre = synth.PRESETS[args.workload]
     dims = pre.dims
     T = dims[3]

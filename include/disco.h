@@ -303,6 +303,13 @@ int disco_laplace_apply(disco_ctx* ctx, int nvec, const void* in, void* out);
  * eigenvector residual ||-Delta v - lambda v|| (<= 0: 1e-12).  ENOCONV when
  * the eigensolver stops above tol. */
 int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vev, double* lambda);
+/* The same on the timeslices tsel[0..nt) only (host ints, distinct): the
+ * Laplacian and the APE smearing act within a timeslice, so each timeslice's
+ * eigenpairs do not depend on the others.  Vev (device, [nt][nv][Vs][3]) and
+ * lambda (host, [nt][nv]) in the order of tsel.  For callers that need the
+ * sources of a few timeslices only (one packing set of a large lattice). */
+int disco_laplace_eigvecs_slices(disco_ctx* ctx, int nv, double tol, const int* tsel, int nt, void* Vev,
+                                 double* lambda);
 /* Perambulator projection tau[k][j][beta][r] = sum_{xs,c} conj(v_j(t_k; xs)_c)
  * X_r(t_k, xs)_{beta,c} for solutions X (device, [nsrc][V][4][3] complex128,
  * nsrc <= 64) at the sink timeslices t_snk[0..n_snk-1] (host ints): the sink

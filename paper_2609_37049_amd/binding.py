@@ -90,6 +90,7 @@ _SIGS.update({
     "disco_smeared_get": ([P, P], I),
     "disco_laplace_apply": ([P, I, P, P], I),
     "disco_laplace_eigvecs": ([P, I, D, P, P], I),
+    "disco_laplace_eigvecs_slices": ([P, I, D, P, I, P, P], I),
     "disco_perambulator": ([P, P, I, I, P, P, I, P], I),
     "disco_loops": ([P, P, I, I, P, P, I, P], I),
     "disco_loops_distill": ([P, P, P, I, P, P, I, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolverStats)], I),
@@ -417,6 +418,16 @@ class Context:
         Vev = torch.empty((T, nv, self.Vs, 3), dtype=torch.complex128, device="cuda:%d" % self.device)
         lam = np.empty((T, nv), dtype=np.float64)
         self._chk(lib().disco_laplace_eigvecs(self.h, int(nv), float(tol), _dptr(Vev), lam.ctypes.data_as(P)))
+        return Vev, lam
+
+    def laplace_eigvecs_slices(self, nv, tsel, tol=1e-12):
+        """Eigenpairs on the timeslices tsel only: ([len(tsel)][nv][Vs][3], [len(tsel)][nv])."""
+        torch = _torch()
+        ts = np.ascontiguousarray(np.asarray(tsel, dtype=np.int32))
+        Vev = torch.empty((len(ts), nv, self.Vs, 3), dtype=torch.complex128, device="cuda:%d" % self.device)
+        lam = np.empty((len(ts), nv), dtype=np.float64)
+        self._chk(lib().disco_laplace_eigvecs_slices(self.h, int(nv), float(tol), ts.ctypes.data_as(P), len(ts),
+                                                     _dptr(Vev), lam.ctypes.data_as(P)))
         return Vev, lam
 
     def perambulator(self, Vev, X, t_snk):

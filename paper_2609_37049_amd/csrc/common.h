@@ -168,6 +168,9 @@ int guarded(disco_ctx* ctx, F&& body) {
 
 // device workspace owned by the context (grow-only, reused across calls)
 void* ws_get(disco_ctx* ctx, const std::string& name, size_t bytes);
+// release a workspace (no-op when absent): set-up buffers and buffers a large
+// solve no longer needs go back to the device allocator
+void ws_free(disco_ctx* ctx, const std::string& name);
 void activate(disco_ctx* ctx);
 
 // launch helpers for profiling

@@ -31,6 +31,15 @@ void* ws_get(disco_ctx* ctx, const std::string& name, size_t bytes) {
     return p;
 }
 
+void ws_free(disco_ctx* ctx, const std::string& name) {
+    auto it = ctx->ws.find(name);
+    if (it == ctx->ws.end()) return;
+    // queued work may still read it
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(it->second.first));
+    ctx->ws.erase(it);
+}
+
 static hipEvent_t ev_get(disco_ctx* ctx) {
     if (!ctx->ev_pool.empty()) {
         hipEvent_t e = ctx->ev_pool.back();

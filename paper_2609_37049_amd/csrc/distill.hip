@@ -163,24 +163,32 @@ __global__ void k_smeared_export(const double2* __restrict__ Usm, const double2*
 
 // ------------------------------------------------------------------ 3-D Laplacian on eigenvector blocks
 // y[t][xs*3+c][j] = sum_k [2 y(x) - U_k(x) y(x+k) - U_k(x-k)^+ y(x-k)]  (within timeslice t)
+// The blocks may hold a subset of the timeslices: block timeslice tb is
+// lattice timeslice tmap[tb] (tmap = NULL: all of them, in order); nsites =
+// sites of the blocks.  The Laplacian acts within a timeslice, so a subset is
+// an exact restriction.
 __global__ void k_laplace(const double2* __restrict__ U, const double2* __restrict__ in, double2* __restrict__ out,
-                          Geo3 g, long V, int m) {
-    const long tot = V * m;
+                          Geo3 g, long V, int m, const int* __restrict__ tmap, long nsites) {
+    const long tot = nsites * m;
+    const long Vs = g.st[3];
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
-        const long s = i / m;
-        const int j = (int)(i - s * m);
+        const long sb_ = i / m;  // site in the blocks
+        const int j = (int)(i - sb_ * m);
+        const long tb = sb_ / Vs;
+        const long shift = tmap ? ((long)tmap[tb] - tb) * Vs : 0;  // lattice site = block site + shift
+        const long s = sb_ + shift;
         int x[4];
         coords(g, s, x);
         cd acc[3];
         for (int c = 0; c < 3; c++) {
-            double2 v = in[(s * 3 + c) * m + j];
+            double2 v = in[(sb_ * 3 + c) * m + j];
             acc[c] = mk(6.0 * v.x, 6.0 * v.y);
         }
         for (int k = 0; k < 3; k++) {
             long sf = nbr(g, s, x[k], k, 1), sb = nbr(g, s, x[k], k, -1);
             cd u[9], yf[3], yb[3];
             for (int c = 0; c < 3; c++) {
-                double2 a = in[(sf * 3 + c) * m + j], b = in[(sb * 3 + c) * m + j];
+                double2 a = in[((sf - shift) * 3 + c) * m + j], b = in[((sb - shift) * 3 + c) * m + j];
                 yf[c] = mk(a.x, a.y);
                 yb[c] = mk(b.x, b.y);
             }
@@ -190,7 +198,7 @@ __global__ void k_laplace(const double2* __restrict__ U, const double2* __restri
             for (int a = 0; a < 3; a++)
                 acc[a] = acc[a] - (cjmul(u[a], yb[0]) + cjmul(u[3 + a], yb[1]) + cjmul(u[6 + a], yb[2]));
         }
-        for (int c = 0; c < 3; c++) out[(s * 3 + c) * m + j] = make_double2(acc[c].re, acc[c].im);
+        for (int c = 0; c < 3; c++) out[(sb_ * 3 + c) * m + j] = make_double2(acc[c].re, acc[c].im);
     }
 }
 
@@ -750,21 +758,40 @@ int disco_laplace_apply(disco_ctx* ctx, int nvec, const void* in, void* out) {
         double2* a = (double2*)ws_get(ctx, "lap_a", sizeof(double2) * V * 3 * nvec);
         double2* b = (double2*)ws_get(ctx, "lap_b", sizeof(double2) * V * 3 * nvec);
         k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>((const double2*)in, a, nvec, T * K, 0);
-        k_laplace<<<grid_for(V * nvec), 256, 0, ctx->stream>>>(U, a, b, geo_of(ctx), V, nvec);
+        k_laplace<<<grid_for(V * nvec), 256, 0, ctx->stream>>>(U, a, b, geo_of(ctx), V, nvec, nullptr, V);
         k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>(b, (double2*)out, nvec, T * K, 1);
         HIPCHK(hipGetLastError());
     });
 }
 
-int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vout, double* lambda) {
+// Eigenpairs on the timeslices tsel[0..nt) (all of them when tsel is NULL),
+// every slice an independent problem solved side by side.
+static int laplace_eigvecs(disco_ctx* ctx, int nv, double tol, const int* tsel, int nt, void* Vout, double* lambda) {
     if (!ctx) return DISCO_EINVAL;
     return guarded(ctx, [&] {
         REQUIRE(ctx->have_gauge, DISCO_ESTATE, "laplace_eigvecs before gauge_set");
         REQUIRE(Vout && lambda, DISCO_EINVAL, "NULL output");
-        const int T = ctx->dims[3];
-        const long Vs = ctx->Vs, V = ctx->V, K = 3 * Vs;
+        const int Tall = ctx->dims[3];
+        const int T = tsel ? nt : Tall;
+        REQUIRE(T >= 1 && T <= Tall, DISCO_EINVAL, "%d timeslices of %d", T, Tall);
+        std::vector<int> tm;
+        if (tsel) {
+            std::vector<int> seen(Tall, 0);
+            for (int k = 0; k < nt; k++) {
+                REQUIRE(tsel[k] >= 0 && tsel[k] < Tall && !seen[tsel[k]], DISCO_EINVAL, "bad timeslice %d", tsel[k]);
+                seen[tsel[k]] = 1;
+                tm.push_back(tsel[k]);
+            }
+        }
+        const long Vs = ctx->Vs, Vl = ctx->V, K = 3 * Vs;
+        const long V = (long)T * Vs;  // sites of the blocks
         REQUIRE(nv >= 1 && nv <= K, DISCO_EINVAL, "nv %d out of range 1..%ld", nv, K);
         activate(ctx);
+        int* tmapd = nullptr;
+        if (tsel) {
+            tmapd = (int*)ws_get(ctx, "eig_tmap", sizeof(int) * T);
+            HIPCHK(hipMemcpyAsync(tmapd, tm.data(), sizeof(int) * T, hipMemcpyHostToDevice, ctx->stream));
+        }
         const double2* U = ctx->have_smeared ? ctx->Usm : ctx->U64;
         const int guard = std::max(4, nv / 4);
         int m = (int)std::min<long>(K, ((nv + guard + 3) / 4) * 4);
@@ -784,7 +811,7 @@ int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vout, double
         std::vector<dense::zc> Gh((size_t)T * m * m), Hh((size_t)T * m * m), Ch;
         std::vector<double> lam, res((size_t)T * nv);
         auto lap = [&](const double2* in, double2* out) {
-            k_laplace<<<grid_for(V * m), 256, 0, ctx->stream>>>(U, in, out, g, V, m);
+            k_laplace<<<grid_for(V * m), 256, 0, ctx->stream>>>(U, in, out, g, Vl, m, tmapd, V);
             HIPCHK(hipGetLastError());
         };
         auto gram = [&](const double2* A, const double2* B, std::vector<dense::zc>& host) {
@@ -864,7 +891,23 @@ int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vout, double
         for (int t = 0; t < T; t++)
             for (int i = 0; i < nv; i++) lambda[(size_t)t * nv + i] = lam[(size_t)t * m + i];
         HIPCHK(hipStreamSynchronize(ctx->stream));
+        // set-up only: the blocks (4 x T K m complex numbers) go back to the allocator
+        for (const char* w : {"eig_Y", "eig_LY", "eig_Y1", "eig_Y2", "eig_G", "eig_C"}) ws_free(ctx, w);
     });
+}
+
+int disco_laplace_eigvecs(disco_ctx* ctx, int nv, double tol, void* Vout, double* lambda) {
+    return laplace_eigvecs(ctx, nv, tol, nullptr, 0, Vout, lambda);
+}
+
+int disco_laplace_eigvecs_slices(disco_ctx* ctx, int nv, double tol, const int* tsel, int nt, void* Vout,
+                                 double* lambda) {
+    if (!ctx) return DISCO_EINVAL;
+    if (!tsel || nt < 1) {
+        ctx->err = "no timeslices";
+        return DISCO_EINVAL;
+    }
+    return laplace_eigvecs(ctx, nv, tol, tsel, nt, Vout, lambda);
 }
 
 int disco_perambulator(disco_ctx* ctx, const void* Vin, int nv, int nsrc, const void* X, const int* t_snk, int n_snk,

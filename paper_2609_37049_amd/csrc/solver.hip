@@ -1360,9 +1360,31 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         int fb = 0;
         int total = iters;
         if (!done && P.fallback) {
-            // the FP64 judge has a budget of its own: max_iter caps the inner iterations
+            // the FP64 judge has a budget of its own: max_iter caps the inner iterations.
+            // Its five FP64 blocks take the place of the inner Krylov vectors, which the
+            // next episode allocates again (at 64 lanes of 32^3 x 64 both do not fit).
             fb = 1;
+            for (const char* wn : {"bi_r", "bi_rh", "bi_p", "bi_v", "bi_s", "bi_t", "bi_eotmp", "eo_re", "eo_ro",
+                                   "eo_uo", "eo_rhat", "eo_ee", "eo_eo", "dc_rin", "dc_e"})
+                ws_free(ctx, wn);
             cgnr_correct(w, b64, x64, r64, mask, P.tol, kFallbackIters, check, &total);
+            for (const char* wn : {"dc_ecg", "cg_r", "cg_z", "cg_p", "cg_w"}) ws_free(ctx, wn);
+            if (feed && next < feed->total) {
+                // the inner vectors of the next episode, re-allocated (the pointers may differ)
+                rin = ws_get(ctx, "dc_rin", nbp);
+                efull = ws_get(ctx, "dc_e", nbp);
+                if (eo) {
+                    re = ws_get(ctx, "eo_re", hb);
+                    ro = ws_get(ctx, "eo_ro", hb);
+                    uo = ws_get(ctx, "eo_uo", hb);
+                    rhat = ws_get(ctx, "eo_rhat", hb);
+                    ee = ws_get(ctx, "eo_ee", hb);
+                    eodd = ws_get(ctx, "eo_eo", hb);
+                } else {
+                    rhat = rin;
+                    ee = efull;
+                }
+            }
         }
         iters_all += total;
         if (feed) {

@@ -86,6 +86,27 @@ def test_eigvecs_parity(disco, dims, nv, steps):
         assert np.abs(A.T @ np.conj(A) - B.T @ np.conj(B)).max() < 1e-8
 
 
+def test_eigvecs_on_chosen_timeslices(disco):
+    """Eigenpairs on a few timeslices only equal those of the all-timeslice
+    solve there (eigenvalues, and the projector onto the eigenvectors, which
+    does not depend on their phases), on smeared links."""
+    dims = (6, 4, 4, 6)
+    U = synth.gauge_field(dims, 0.4, 17)
+    ctx = _ctx(disco, dims, U)
+    ctx.ape_smear(2, 0.5)
+    Vg, lam = ctx.laplace_eigvecs(5, 1e-13)
+    ts = [4, 1, 5]
+    Vs_, lam_s = ctx.laplace_eigvecs_slices(5, ts, 1e-13)
+    Vg, Vs_ = Vg.cpu().numpy(), Vs_.cpu().numpy()
+    for k, t in enumerate(ts):
+        assert np.abs(lam_s[k] - lam[t]).max() < 1e-11
+        A = Vg[t].reshape(5, -1)
+        B = Vs_[k].reshape(5, -1)
+        assert np.abs(A.T @ np.conj(A) - B.T @ np.conj(B)).max() < 1e-9
+    with pytest.raises(disco.DiscoError):
+        ctx.laplace_eigvecs_slices(5, [1, 1])
+
+
 def test_perambulator_parity(disco):
     """Same V and X on both sides: tau = V^+ X at several sink timeslices (FP64 MFMA)."""
     dims = (6, 4, 4, 5)
