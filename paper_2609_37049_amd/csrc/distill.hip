@@ -167,50 +167,107 @@ __global__ void k_smeared_export(const double2* __restrict__ Usm, const double2*
 // lattice timeslice tmap[tb] (tmap = NULL: all of them, in order); nsites =
 // sites of the blocks.  The Laplacian acts within a timeslice, so a subset is
 // an exact restriction.
-__global__ void k_laplace(const double2* __restrict__ U, const double2* __restrict__ in, double2* __restrict__ out,
-                          Geo3 g, long V, int m, const int* __restrict__ tmap, long nsites) {
-    const long tot = nsites * m;
-    const long Vs = g.st[3];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
-        const long sb_ = i / m;  // site in the blocks
-        const int j = (int)(i - sb_ * m);
-        const long tb = sb_ / Vs;
-        const long shift = tmap ? ((long)tmap[tb] - tb) * Vs : 0;  // lattice site = block site + shift
-        const long s = sb_ + shift;
-        int x[4];
-        coords(g, s, x);
-        cd acc[3];
+//
+// A workgroup takes kLapSites consecutive block sites: it first copies their
+// six links (U_k(x) and U_k(x-k), k = 1..3) into LDS, then runs one thread per
+// (site, vector j), j fastest, so that a wavefront reads each neighbour row of
+// m vectors contiguously and the m threads of a site share one copy of its
+// links.  Index arithmetic is 32-bit: the caller guarantees 3 nsites m < 2^31.
+// CHEB: one step of the Chebyshev filter fused in, out = a (L y - c y) + b prev
+// (prev NULL reads as 0); otherwise out = L y.
+constexpr int kLapSites = 16;
+
+struct LapSite {
+    unsigned bb;  // first block site of the timeslice
+    unsigned lb;  // first lattice site of the timeslice
+    unsigned xs;  // site within the timeslice
+    unsigned x[3];
+};
+
+__device__ __forceinline__ LapSite lap_site(const Geo3& g, const int* tmap, unsigned sb_) {
+    const unsigned Vs = (unsigned)g.st[3], L0 = (unsigned)g.L[0], L1 = (unsigned)g.L[1];
+    LapSite o;
+    const unsigned tb = sb_ / Vs;
+    o.xs = sb_ - tb * Vs;
+    o.bb = tb * Vs;
+    o.lb = (tmap ? (unsigned)tmap[tb] : tb) * Vs;
+    const unsigned q = o.xs / L0;
+    o.x[0] = o.xs - q * L0;
+    o.x[1] = q % L1;
+    o.x[2] = q / L1;
+    return o;
+}
+
+// spatial neighbour of xs in direction k (d = +1 forward, -1 backward), periodic
+__device__ __forceinline__ unsigned lap_nbr(const Geo3& g, const LapSite& p, int k, int d) {
+    const unsigned L = (unsigned)g.L[k], st = (unsigned)g.st[k];
+    if (d > 0) return p.x[k] + 1 == L ? p.xs - (L - 1) * st : p.xs + st;
+    return p.x[k] == 0 ? p.xs + (L - 1) * st : p.xs - st;
+}
+
+template <bool CHEB>
+__global__ __launch_bounds__(256) void k_laplace(const double2* __restrict__ U, const double2* __restrict__ in,
+                                                 double2* __restrict__ out, Geo3 g, long V, int m,
+                                                 const int* __restrict__ tmap, int nsites,
+                                                 const double2* __restrict__ prev, double ca, double cc, double cb) {
+    __shared__ double2 su[kLapSites][6][9];
+    const unsigned mm = (unsigned)m;
+    const unsigned s0 = blockIdx.x * kLapSites;
+    const unsigned ns = min((unsigned)kLapSites, (unsigned)nsites - s0);
+    for (unsigned e = threadIdx.x; e < ns * 54; e += blockDim.x) {
+        const unsigned ls = e / 54, r = e - ls * 54, h = r / 9, q = r - h * 9;
+        const LapSite p = lap_site(g, tmap, s0 + ls);
+        const int k = (int)(h % 3);
+        const unsigned site = p.lb + (h < 3 ? p.xs : lap_nbr(g, p, k, -1));
+        su[ls][h][q] = U[((size_t)k * 9 + q) * (size_t)V + site];
+    }
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < ns * mm; e += blockDim.x) {
+        const unsigned ls = e / mm, j = e - ls * mm;
+        const unsigned sb_ = s0 + ls;  // site in the blocks
+        const LapSite p = lap_site(g, tmap, sb_);
+        cd y0[3], acc[3];
+#pragma unroll
         for (int c = 0; c < 3; c++) {
-            double2 v = in[(sb_ * 3 + c) * m + j];
+            const double2 v = in[(sb_ * 3 + c) * mm + j];
+            y0[c] = mk(v.x, v.y);
             acc[c] = mk(6.0 * v.x, 6.0 * v.y);
         }
+#pragma unroll
         for (int k = 0; k < 3; k++) {
-            long sf = nbr(g, s, x[k], k, 1), sb = nbr(g, s, x[k], k, -1);
+            const unsigned xf = p.bb + lap_nbr(g, p, k, 1), xb = p.bb + lap_nbr(g, p, k, -1);
             cd u[9], yf[3], yb[3];
+#pragma unroll
             for (int c = 0; c < 3; c++) {
-                double2 a = in[((sf - shift) * 3 + c) * m + j], b = in[((sb - shift) * 3 + c) * m + j];
+                const double2 a = in[(xf * 3 + c) * mm + j], b = in[(xb * 3 + c) * mm + j];
                 yf[c] = mk(a.x, a.y);
                 yb[c] = mk(b.x, b.y);
             }
-            ldU(U, V, k, s, u);
+#pragma unroll
+            for (int q = 0; q < 9; q++) u[q] = mk(su[ls][k][q].x, su[ls][k][q].y);
+#pragma unroll
             for (int a = 0; a < 3; a++) acc[a] = acc[a] - (u[a * 3] * yf[0] + u[a * 3 + 1] * yf[1] + u[a * 3 + 2] * yf[2]);
-            ldU(U, V, k, sb, u);
+#pragma unroll
+            for (int q = 0; q < 9; q++) u[q] = mk(su[ls][3 + k][q].x, su[ls][3 + k][q].y);
+#pragma unroll
             for (int a = 0; a < 3; a++)
                 acc[a] = acc[a] - (cjmul(u[a], yb[0]) + cjmul(u[3 + a], yb[1]) + cjmul(u[6 + a], yb[2]));
         }
-        for (int c = 0; c < 3; c++) out[(sb_ * 3 + c) * m + j] = make_double2(acc[c].re, acc[c].im);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const unsigned o = (sb_ * 3 + c) * mm + j;
+            if constexpr (CHEB) {
+                const double2 q = prev ? prev[o] : make_double2(0, 0);
+                out[o] = make_double2(ca * (acc[c].re - cc * y0[c].re) + cb * q.x,
+                                      ca * (acc[c].im - cc * y0[c].im) + cb * q.y);
+            } else {
+                out[o] = make_double2(acc[c].re, acc[c].im);
+            }
+        }
     }
 }
 
-// Chebyshev step: out = a * (L y - c y) + b * prev   (L y given in ly)
-__global__ void k_cheb(const double2* __restrict__ ly, const double2* __restrict__ y, const double2* __restrict__ prev,
-                       double2* __restrict__ out, long n, double a, double c, double b) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        double2 l = ly[i], v = y[i];
-        double2 p = prev ? prev[i] : make_double2(0, 0);
-        out[i] = make_double2(a * (l.x - c * v.x) + b * p.x, a * (l.y - c * v.y) + b * p.y);
-    }
-}
+static int lap_grid(long nsites) { return (int)((nsites + kLapSites - 1) / kLapSites); }
 
 // deterministic pseudo-random start vectors (splitmix64 of the element index)
 __global__ void k_rand_fill(double2* y, long n, unsigned long long seed) {
@@ -758,7 +815,9 @@ int disco_laplace_apply(disco_ctx* ctx, int nvec, const void* in, void* out) {
         double2* a = (double2*)ws_get(ctx, "lap_a", sizeof(double2) * V * 3 * nvec);
         double2* b = (double2*)ws_get(ctx, "lap_b", sizeof(double2) * V * 3 * nvec);
         k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>((const double2*)in, a, nvec, T * K, 0);
-        k_laplace<<<grid_for(V * nvec), 256, 0, ctx->stream>>>(U, a, b, geo_of(ctx), V, nvec, nullptr, V);
+        REQUIRE(3.0 * (double)V * nvec < 2147483648.0, DISCO_EINVAL, "%d vectors of %ld sites: too large", nvec, V);
+        k_laplace<false><<<lap_grid(V), 256, 0, ctx->stream>>>(U, a, b, geo_of(ctx), V, nvec, nullptr, (int)V, nullptr,
+                                                              1.0, 0.0, 0.0);
         k_blk_transpose<<<grid_for(V * 3 * nvec), 256, 0, ctx->stream>>>(b, (double2*)out, nvec, T * K, 1);
         HIPCHK(hipGetLastError());
     });
@@ -810,8 +869,15 @@ static int laplace_eigvecs(disco_ctx* ctx, int nv, double tol, const int* tsel, 
         k_rand_fill<<<gY, 256, 0, ctx->stream>>>(Y, (long)nY, 0x5eed1234ULL);
         std::vector<dense::zc> Gh((size_t)T * m * m), Hh((size_t)T * m * m), Ch;
         std::vector<double> lam, res((size_t)T * nv);
+        REQUIRE(3.0 * (double)V * m < 2147483648.0, DISCO_EINVAL, "%d vectors of %ld sites: too large", m, V);
         auto lap = [&](const double2* in, double2* out) {
-            k_laplace<<<grid_for(V * m), 256, 0, ctx->stream>>>(U, in, out, g, Vl, m, tmapd, V);
+            k_laplace<false><<<lap_grid(V), 256, 0, ctx->stream>>>(U, in, out, g, Vl, m, tmapd, (int)V, nullptr, 1.0,
+                                                                  0.0, 0.0);
+            HIPCHK(hipGetLastError());
+        };
+        // out = a (L in - c in) + b prev: a Chebyshev step with the Laplacian fused in
+        auto lapcheb = [&](const double2* in, const double2* prev, double2* out, double a, double c, double b) {
+            k_laplace<true><<<lap_grid(V), 256, 0, ctx->stream>>>(U, in, out, g, Vl, m, tmapd, (int)V, prev, a, c, b);
             HIPCHK(hipGetLastError());
         };
         auto gram = [&](const double2* A, const double2* B, std::vector<dense::zc>& host) {
@@ -841,7 +907,14 @@ static int laplace_eigvecs(disco_ctx* ctx, int nv, double tol, const int* tsel, 
         };
         double worst = rr();
         const double upper = 12.0;  // spectrum of -Delta lies in [0, 12]
-        const int degree = 12;
+        // Degree: near convergence the wanted end of the spectrum sits just below
+        // a, where a Chebyshev polynomial grows only quadratically with its
+        // degree until degree x acosh(x) passes 1; 32 keeps the growth in the
+        // exponential regime (on smeared 24^3 slices with 64 + 16 vectors: 27
+        // filter steps and 864 Laplacians to 1e-11, against 119 and 1428 at
+        // degree 12) while the spread it puts between the wanted columns stays
+        // far from what Cholesky QR in FP64 resolves.
+        const int degree = 32;
         const double want = tol > 0 ? tol : 1e-12;
         for (int it = 0; it < 400 && worst > want; it++) {
             // Chebyshev filter damping [a, upper], a = largest current Ritz value over the slices
@@ -850,12 +923,10 @@ static int laplace_eigvecs(disco_ctx* ctx, int nv, double tol, const int* tsel, 
             a = std::min(a, 0.9 * upper);
             const double e = (upper - a) / 2, c = (upper + a) / 2;
             // T1 = (L - c) Y / e ; T_{k+1} = 2 (L - c) T_k / e - T_{k-1}
-            lap(Y, LY);
-            k_cheb<<<gY, 256, 0, ctx->stream>>>(LY, Y, nullptr, Y1, (long)nY, 1.0 / e, c, 0.0);
+            lapcheb(Y, nullptr, Y1, 1.0 / e, c, 0.0);
             double2 *prev = Y, *cur = Y1, *nxt = Y2;
             for (int k = 1; k < degree; k++) {
-                lap(cur, LY);
-                k_cheb<<<gY, 256, 0, ctx->stream>>>(LY, cur, prev, nxt, (long)nY, 2.0 / e, c, -1.0);
+                lapcheb(cur, prev, nxt, 2.0 / e, c, -1.0);
                 double2* t0 = prev;
                 prev = cur;
                 cur = nxt;
