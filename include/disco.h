@@ -82,7 +82,10 @@ enum {
                             * inner_tol (default 3e-2 for BF16, 1e-3 for FP32) the corrections
                             * are folded into the FP64 solution, the FP64 true residual replaces
                             * the recursive one and the process continues (lanes that break
-                            * down or stall restart it); even-odd as for BICGSTAB_DC.  The
+                            * down or stall restart it; a correction that leaves a lane's true
+                            * residual more than 4x above the previous update's is taken back
+                            * and that lane restarts with a perturbed shadow residual);
+                            * even-odd as for BICGSTAB_DC.  The
                             * right-hand sides of a call form one queue: a lane whose right-hand
                             * side has converged takes the next one at that update, so no lane
                             * waits for the slowest of its block */

@@ -41,7 +41,8 @@ struct RhsScal {
     int reached;  // reliable updates: the inner residual has fallen by inner_tol since the last update
     double best;  // smallest inner ||r||^2 since it last halved (reliable updates)
     int since;    // inner iterations since then
-    int pad2;
+    int reject;   // reliable updates: 1 = the last correction left the true residual far above the one
+                  // before (it is taken back), 2 = the lane then restarts with a perturbed shadow residual
 };
 
 // inner iterations without a halving of a lane's inner residual before it
@@ -49,6 +50,10 @@ struct RhsScal {
 constexpr int kRuStall = 100;
 // iterations the FP64 CGNR fallback of the reliable-update solver may take
 constexpr int kFallbackIters = 100000;
+// reliable updates: a lane whose true ||r||^2 after the fold-in exceeds this
+// multiple of its value at the previous update (4x in norm) gets the
+// correction taken back, and its Krylov process restarts from the old iterate
+constexpr double kRejectGrowth = 16.0;
 // threads of a per-RHS scalar step (one block per right-hand side folds its
 // partial sums; more threads keep more loads in flight)
 constexpr int kScalarBlock = 1024;
@@ -161,14 +166,15 @@ __global__ void k_copy_scale(const void* src, void* dst, long V, int n, const Rh
 }
 
 // x64 += (1/scale[r]) * e (inner precision) for right-hand sides that ran
-// (not for finished ones, nor for inner solves that diverged)
-template <class IO>
+// (not for finished ones, nor for inner solves that diverged).  UNDO: x64 -=
+// the same, for the lanes whose correction is rejected.
+template <class IO, bool UNDO = false>
 __global__ void k_dc_update(double2* x64, const void* e, long V, int n, const RhsScal* sc) {
     const long tot = V * n;
     for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
         const long s = j / n, r = j - s * n;
-        if (sc[r].outer_done || sc[r].breakdown == 2) continue;
-        const double f = sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0;
+        if (UNDO ? sc[r].reject != 1 : (sc[r].outer_done || sc[r].breakdown == 2)) continue;
+        const double f = (sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0) * (UNDO ? -1.0 : 1.0);
         cx<typename IO::T> a[12];
         cx<double> x[12];
         IO::load(e, V, n, r, s, a);
@@ -245,6 +251,18 @@ __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, c
     rhs_partials<1>(acc, g.n, g.bd, part, g.nb, blockIdx.x);
 }
 
+// uniform in [-1, 1) from a 32-bit integer hash of (k, salt) (the "lowbias32"
+// mixing function: xor-shifts and two odd multipliers)
+__device__ __forceinline__ double unit_hash(unsigned k, unsigned salt) {
+    unsigned x = k ^ (salt * 0x9e3779b9u);
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return (double)(x >> 8) * (1.0 / 8388608.0) - 1.0;
+}
+
 // Reliable update of the inner BiCGStab (continued, not restarted): the
 // recursive residual r is replaced by rn, the residual of the inner system
 // recomputed from the FP64 true residual; p, built from the old r, takes the
@@ -253,11 +271,15 @@ __global__ void k_bicg_xrp(void* x_, void* p_, const void* s_, const void* t_, c
 // instead: p = rhat = rn.  Partials <rhat, rn>, ||rn||^2.
 template <class IO>
 __global__ void k_ru_refresh(void* r_, const void* rn_, void* p_, void* rh_, void* e_, VecGeo g, const RhsScal* sc,
-                             double2* part) {
+                             double2* part, unsigned salt) {
     typedef Unit<IO> U;
     typedef typename IO::T T;
     const int rr = threadIdx.x % g.n;
     const bool restart = sc[rr].breakdown || sc[rr].outer_done;
+    // a lane whose last correction was taken back: r^ = r (1 + xi / 2) component
+    // by component, xi uniform in [-1, 1) from a hash of (unit, component,
+    // update), so that <r^, r> stays a positive multiple of ||r||^2
+    const bool perturb = restart && sc[rr].reject == 2;
     double acc[4] = {0, 0, 0, 0};
     cx<T> z[U::C];
 #pragma unroll
@@ -270,6 +292,10 @@ __global__ void k_ru_refresh(void* r_, const void* rn_, void* p_, void* rh_, voi
             for (int c = 0; c < U::C; c++) {
                 p[c] = rn[c];
                 rh[c] = rn[c];
+                if (perturb) {
+                    const T f = (T)(1.0 + 0.5 * unit_hash((unsigned)i * (unsigned)U::C + (unsigned)c, salt));
+                    rh[c] = mk(f * rn[c].re, f * rn[c].im);
+                }
             }
             U::st(rh_, i, rh);
         } else {
@@ -382,9 +408,28 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
         s.rr = q[0].re;
         s.gam = q[0].re;
         s.outer_done = 0;
+        s.reject = 0;
     } else {
         s.rr = q[0].re;
     }
+    if (mode == 2 && !s.outer_done && s.gam > 0 && !(s.rr <= kRejectGrowth * s.gam)) {
+        // the correction made things worse (or is not a number): it is taken
+        // back and the true residual recomputed before the rest (mode 3)
+        s.reject = 1;
+        return;
+    }
+    if (mode == 3 && s.reject == 1) {
+        // the restored iterate: its Krylov process restarts, with another
+        // shadow residual (from the same state, r^ = r would retrace the same
+        // iterations)
+        s.reject = 2;
+        s.breakdown = 1;
+        s.gam = s.rr;
+        if (s.rr <= tol2 * s.bb) s.outer_done = 1;
+        if (s.outer_done) s.scale = 0.0;
+        return;
+    }
+    if (mode == 3) return;
     if (mode == 2) {
         if (!s.outer_done && (s.reached || !s.active) && !s.breakdown && s.rr > 0.5 * s.gam) s.breakdown = 1;
         s.gam = s.rr;
@@ -432,6 +477,7 @@ __global__ void k_sc_lane_start(const double2* part, int nparts, RhsScal* sc, co
     s.breakdown = 1;
     s.reached = 0;
     s.active = 0;
+    s.reject = 0;
 }
 
 // one right-hand side in the canonical layout [V][12] <-> lane r of a native FP64 block
@@ -464,6 +510,7 @@ __global__ void k_sc_ru_refresh(const double2* part, int nparts, RhsScal* sc) {
     s.since = 0;
     s.breakdown = 0;
     s.reached = 0;
+    s.reject = 0;
     s.active = (!s.outer_done && s.irr > 0) ? 1 : 0;
     s.alpha = s.omega = s.beta = mk(0.0, 0.0);
 }
@@ -899,16 +946,17 @@ __global__ void k_scale_split(const double2* __restrict__ full, void* __restrict
     }
 }
 // k_eo_merge and k_dc_update in one pass: x64 += (1/scale[r]) e with e read
-// from its even and odd halves (same lanes skipped as k_dc_update).
-template <class IO>
+// from its even and odd halves (same lanes skipped, and the same UNDO, as
+// k_dc_update).
+template <class IO, bool UNDO = false>
 __global__ void k_dc_update_eo(double2* __restrict__ x64, const void* __restrict__ he, const void* __restrict__ ho,
                                long V, int n, const RhsScal* __restrict__ sc, int Lx, int Ly, int Lz) {
     const long tot = V * n;
     for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < tot; j += (long)gridDim.x * blockDim.x) {
         const long st = j / n;
         const int r = (int)(j - st * n);
-        if (sc[r].outer_done || sc[r].breakdown == 2) continue;
-        const double f = sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0;
+        if (UNDO ? sc[r].reject != 1 : (sc[r].outer_done || sc[r].breakdown == 2)) continue;
+        const double f = (sc[r].scale > 0 ? 1.0 / sc[r].scale : 0.0) * (UNDO ? -1.0 : 1.0);
         cx<typename IO::T> a[12];
         cx<double> x[12];
         IO::load(parity_of(st, Lx, Ly, Lz) ? ho : he, V / 2, n, r, (int)(st >> 1), a);
@@ -1202,6 +1250,27 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
         k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 2, tol2);
         pull(w);
+        // a correction that raised its lane's true residual far above the last
+        // update's is taken back (the inner process went astray; folding it in
+        // would leave the lane further from the solution than before)
+        int nrej = 0;
+        for (const auto& h : w.h) nrej += h.reject == 1;
+        if (nrej) {
+            if (trace)
+                for (int i = 0; i < n; i++)
+                    if (w.h[i].reject == 1)
+                        fprintf(stderr, "[disco] lane %d: correction taken back (true residual %.3e, before %.3e)\n",
+                                i, std::sqrt(w.h[i].rr / w.h[i].bb), std::sqrt(w.h[i].gam / w.h[i].bb));
+            if (eo)
+                hipLaunchKernelGGL((k_dc_update_eo<IO, true>), dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, x64,
+                                   ee, eodd, V, n, w.sc, Lx, Ly, Lz);
+            else
+                hipLaunchKernelGGL((k_dc_update<IO, true>), dim3(site_grid(V, n)), dim3(256), 0, ctx->stream, x64,
+                                   efull, V, n, w.sc);
+            stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
+            k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 3, tol2);
+            pull(w);
+        }
     };
     InnerOp op;
     op.eo = eo;
@@ -1313,6 +1382,18 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
             if (trace) {
                 fprintf(stderr, "[disco] reliable update %d at iteration %d: worst true rel residual %.3e\n", outer, it,
                         worst);
+                // the three lanes furthest from their tolerance, with the state their inner process left
+                std::vector<int> ord;
+                for (int i = 0; i < w.n; i++)
+                    if (!w.h[i].outer_done && w.h[i].bb > 0) ord.push_back(i);
+                std::sort(ord.begin(), ord.end(),
+                          [&](int a, int b) { return w.h[a].rr / w.h[a].bb > w.h[b].rr / w.h[b].bb; });
+                for (size_t q = 0; q < ord.size() && q < 3; q++) {
+                    const RhsScal& h = w.h[ord[q]];
+                    fprintf(stderr, "[disco]   lane %d: true %.3e inner %.3e of %.3e, active %d reached %d breakdown %d\n",
+                            ord[q], std::sqrt(h.rr / h.bb), std::sqrt(h.irr), std::sqrt(h.ibb), h.active, h.reached,
+                            h.breakdown);
+                }
                 for (int i = 0; i < w.n; i++)
                     if (w.h[i].outer_done && !done_at[i])
                         fprintf(stderr, "[disco] lane %d done at iteration %d\n", i, it);
@@ -1341,7 +1422,7 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
             void* rh = ws_get(ctx, "bi_rh", nbp);
             void* p = ws_get(ctx, "bi_p", nbp);
             hipLaunchKernelGGL(k_ru_refresh<IO>, dim3(gh.nb), dim3(gh.bd), 0, ctx->stream, r, rhat, p, rh, ee, gh,
-                               w.sc, w.part);
+                               w.sc, w.part, (unsigned)outer);
             k_sc_ru_refresh<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, gh.nb, w.sc);
             HIPCHK(hipGetLastError());
             return true;
