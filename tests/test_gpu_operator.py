@@ -244,3 +244,38 @@ def test_site_order_tiles_keep_the_operator_bit_for_bit(disco):
     assert dims[1] % yt == 0 and 2 % tt == 0
     for a, b in zip(outputs(), ref):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,n_big,n_small", [("bf16", 128, 32), ("f32", 64, 16)])
+def test_native_apply_without_descriptors_matches_with(disco, prec, n_big, n_small):
+    """Blocks of more than 4 GiB (all planes together) are read with plain
+    global loads instead of buffer descriptors.  At V = 32^4 a block of n_big
+    right-hand sides (6.4 GB) takes that path, a block of n_small (1.6 GB) the
+    descriptor path; each lane's arithmetic is the same, so the n_big result
+    must equal, bit for bit, the n_small results of the same lanes."""
+    import torch
+    dims = (32, 32, 32, 32)
+    V = int(np.prod(dims))
+    p = {"bf16": disco.BF16, "f32": disco.F32}[prec]
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(synth.gauge_field(dims, 0.25, 31))
+    ctx.clover_setup(0.125, 1.5)
+    assert ctx.native_bytes(p, n_big) > 1 << 32 > ctx.native_bytes(p, n_small)
+    planes = {"bf16": 3, "f32": 6}[prec]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    if prec == "bf16":
+        # random bf16 payloads, exponent kept below the top half so that every value is finite
+        x = torch.randint(-2 ** 15, 2 ** 15, (planes, V, n_big, 8), dtype=torch.int16, device="cuda", generator=g)
+        x.bitwise_and_(0x3fff)
+    else:
+        x = (torch.rand((planes, V, n_big, 4), device="cuda", generator=g) - 0.5)
+    y = torch.empty_like(x)
+    ctx.dirac_apply_native(None, p, x, y, n_big)
+    for q in range(n_big // n_small):
+        xs = x[:, :, q * n_small:(q + 1) * n_small].contiguous()
+        ys = torch.empty_like(xs)
+        ctx.dirac_apply_native(None, p, xs, ys, n_small)
+        same = torch.equal(ys.view(torch.int32), y[:, :, q * n_small:(q + 1) * n_small].contiguous().view(torch.int32))
+        assert same, "lanes %d..%d differ" % (q * n_small, (q + 1) * n_small - 1)
+    assert int(y.view(torch.int32).count_nonzero()) > 0
