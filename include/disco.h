@@ -230,8 +230,13 @@ enum {
                            * order: each site's arithmetic is unchanged, so operator outputs
                            * are the same bit for bit; the solvers' fused sums group sites by
                            * this order and change by rounding */
-    DISCO_OPT_TILE_T = 5  /* timeslices per tile inside the slab (a divisor of it; 0 = the whole
+    DISCO_OPT_TILE_T = 5, /* timeslices per tile inside the slab (a divisor of it; 0 = the whole
                            * slab).  disco_autotune sets both */
+    DISCO_OPT_NARROW = 6  /* 1 (default): once the queue of a BICGSTAB_RU call is empty and at
+                           * most half of the block's lanes are still open, those lanes move
+                           * into a block of half the width (down to 16) and restart their
+                           * Krylov processes from their current iterates; 0: the block keeps
+                           * its width to the end */
 };
 int disco_set_option(disco_ctx* ctx, int option, int value);
 /* The current value of an option; for the tile options, the extents the site

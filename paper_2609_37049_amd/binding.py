@@ -26,7 +26,7 @@ K_STENCIL = 0
 K_NN = 2
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_BF16 = 10, 11, 12
 K_MFMA = 1
-OPT_GRAPHS, OPT_STAGE, OPT_EO, OPT_TILE_Y, OPT_TILE_T = 1, 2, 3, 4, 5
+OPT_GRAPHS, OPT_STAGE, OPT_EO, OPT_TILE_Y, OPT_TILE_T, OPT_NARROW = 1, 2, 3, 4, 5, 6
 K_STENCIL_EO_F64, K_STENCIL_EO_F32, K_STENCIL_EO_BF16 = 13, 14, 15
 
 

@@ -112,6 +112,7 @@ struct disco_ctx {
     int opt_graphs = 1;   // capture inner Krylov iteration chunks as HIP graphs
     int opt_stage = -1;   // LDS staging of links/clover in the stencil: -1 auto, 0 off, 1 on
     int opt_eo = 1;       // even-odd (Schur) preconditioned inner solves when every extent is even
+    int opt_narrow = 1;   // reliable updates: narrow the block for the queue's tail
     // graph cache: key -> executable graph; private capture stream
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;

@@ -537,6 +537,9 @@ int disco_set_option(disco_ctx* ctx, int option, int value) {
         } else if (option == DISCO_OPT_EO) {
             REQUIRE(value == 0 || value == 1, DISCO_EINVAL, "even-odd option is 0 or 1");
             ctx->opt_eo = value;
+        } else if (option == DISCO_OPT_NARROW) {
+            REQUIRE(value == 0 || value == 1, DISCO_EINVAL, "narrow option is 0 or 1");
+            ctx->opt_narrow = value;
         } else if (option == DISCO_OPT_TILE_Y || option == DISCO_OPT_TILE_T) {
             REQUIRE(value >= 0 && value <= 255, DISCO_EINVAL, "tile extent %d", value);
             activate(ctx);
@@ -561,6 +564,7 @@ int disco_get_option(const disco_ctx* ctx, int option, int* value) {
         case DISCO_OPT_GRAPHS: *value = ctx->opt_graphs; break;
         case DISCO_OPT_STAGE: *value = ctx->opt_stage; break;
         case DISCO_OPT_EO: *value = ctx->opt_eo; break;
+        case DISCO_OPT_NARROW: *value = ctx->opt_narrow; break;
         case DISCO_OPT_TILE_Y: *value = ctx->tile_used[0]; break;
         case DISCO_OPT_TILE_T: *value = ctx->tile_used[1]; break;
         default: return DISCO_EINVAL;

@@ -50,6 +50,8 @@ struct RhsScal {
 constexpr int kRuStall = 100;
 // iterations the FP64 CGNR fallback of the reliable-update solver may take
 constexpr int kFallbackIters = 100000;
+// the narrowest block the tail of a reliable-update queue moves into
+constexpr int kNarrowMin = 16;
 // reliable updates: a lane whose true ||r||^2 after the fold-in exceeds this
 // multiple of its value at the previous update (4x in norm) gets the
 // correction taken back, and its Krylov process restarts from the old iterate
@@ -430,6 +432,15 @@ __global__ void k_sc_outer(const double2* part, int nparts, RhsScal* sc, int mod
         return;
     }
     if (mode == 3) return;
+    if (mode == 4) {
+        // a lane carried into a narrower block: the residual of its current
+        // iterate starts the new process and sets the inner scale
+        s.gam = s.rr;
+        s.reject = 0;
+        if (s.rr <= tol2 * s.bb) s.outer_done = 1;
+        s.scale = (s.rr > 0 && !s.outer_done) ? 1.0 / sqrt(s.rr) : 0.0;
+        return;
+    }
     if (mode == 2) {
         if (!s.outer_done && (s.reached || !s.active) && !s.breakdown && s.rr > 0.5 * s.gam) s.breakdown = 1;
         s.gam = s.rr;
@@ -450,6 +461,18 @@ __global__ void k_lane_restart(double2* __restrict__ x64, double2* __restrict__ 
         const long j = row * n + lanes[i - row * m];
         x64[j] = make_double2(0.0, 0.0);
         r64[j] = b64[j];
+    }
+}
+
+// dst (width n2) lane q = src (width n) lane lanes[q] for q < m, 0 for the
+// other lanes: the open lanes of a block moved into a narrower one
+__global__ void k_lanes_compact(const double2* __restrict__ src, double2* __restrict__ dst, long V, int n, int n2,
+                                const int* __restrict__ lanes, int m) {
+    const long tot = 12 * V * n2;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long row = i / n2;
+        const int q = (int)(i - row * n2);
+        dst[i] = q < m ? src[row * n + lanes[q]] : make_double2(0.0, 0.0);
     }
 }
 
@@ -1186,19 +1209,33 @@ static void dc_solve(Work& w, const disco_solver_params& P, int prec, const doub
 // the lanes in flight get the FP64 fallback (when allowed) and are handed
 // over, and the rest of the queue runs on in a fresh Krylov process: one hard
 // right-hand side does not cost the ones behind it.
+static Work make_work(disco_ctx* ctx, int n) {
+    Work w;
+    w.ctx = ctx;
+    w.n = n;
+    w.V = ctx->V;
+    w.nsb = disco::stencil_nsb(ctx, n);
+    w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
+    VecGeo g = vgeo(ctx->V, DISCO_F64, n);
+    size_t slots = (size_t)std::max(std::max(w.nsb, disco::stencil_nsb(ctx, n, true)), g.nb);
+    w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 4 * n);
+    HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
+    return w;
+}
+
 template <class IO>
 static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b64, double2* x64,
                      const uint8_t* mask, disco_solver_stats* st, disco::LaneFeeder* feed = nullptr,
                      long long* block_iters = nullptr) {
     disco_ctx* ctx = w.ctx;
-    const int n = w.n;
+    int n = w.n;  // the block's width (narrower for the tail of a queue)
     const long V = w.V;
     const size_t nb64 = disco::native_bytes(ctx, DISCO_F64, n);
     const size_t nbp = disco::native_bytes(ctx, prec, n);
     double2* r64 = (double2*)ws_get(ctx, "dc_r64", nb64);
     void* rin = ws_get(ctx, "dc_rin", nbp);
     void* efull = ws_get(ctx, "dc_e", nbp);
-    const VecGeo g64 = vgeo(V, DISCO_F64, n);
+    VecGeo g64 = vgeo(V, DISCO_F64, n);
     const double tol2 = P.tol * P.tol;
     const int check = P.check_every > 0 ? P.check_every : 2;
     const double delta = P.inner_tol > 0 ? P.inner_tol : (prec == DISCO_BF16 ? 3e-2 : 1e-3);
@@ -1277,14 +1314,20 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
     op.Vv = Vv;
     op.nsb = disco::stencil_nsb(ctx, n, eo);
     long long iters_all = 0;
+    // carry: the episode continues the open lanes of a wider block (their x64
+    // and b64 already moved into lanes 0..held-1), instead of loading the queue
+    bool carry = false;
+    int carried = 0;
     // one episode per Krylov process of the block (a single one unless the
-    // block stops before the queue is empty)
+    // block stops before the queue is empty, or narrows for its tail)
     for (;;) {
         int outer = 0, stall = 0, it_best = 0;
         double last_worst = 1e300;
-        bool gave_up = false;
+        bool gave_up = false, narrowing = false;
         int held = 0;
-        if (feed) {
+        if (feed && carry) {
+            held = carried;
+        } else if (feed) {
             // fill every lane from the queue; lanes left idle get b = 0 (they
             // may still hold a right-hand side of the previous episode), which
             // marks them finished at the start
@@ -1306,10 +1349,18 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
                 hipLaunchKernelGGL(k_lane_clear, dim3(1024), dim3(256), 0, ctx->stream, b64, V, n, dlane, m);
             }
         }
-        k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
-        norm2<IO64>(w, b64, g64);
-        k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
-        copy_scale<IO64, IO64>(w, b64, r64, 0);
+        if (carry) {
+            norm2<IO64>(w, b64, g64);
+            k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+            stencil(w, DISCO_F64, 0, x64, r64, b64, nullptr, mask, disco::EPI_RESID | disco::EPI_NORM);
+            k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, w.nsb, w.sc, 4, tol2);
+            carry = false;
+        } else {
+            k_zero<IO64><<<1024, 256, 0, ctx->stream>>>(x64, g64.total);
+            norm2<IO64>(w, b64, g64);
+            k_sc_outer<<<n, kScalarBlock, 0, ctx->stream>>>(w.part, g64.nb, w.sc, 0, tol2);
+            copy_scale<IO64, IO64>(w, b64, r64, 0);
+        }
         // with a queue the cap applies per wave of the right-hand sides this
         // episode starts with or still has to take
         const int waves = feed ? std::max(1, (held + (feed->total - next) + n - 1) / n) : 1;
@@ -1416,6 +1467,18 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
                 gave_up = true;
                 return false;
             }
+            // the queue is empty and at most half of the lanes are open: they
+            // move into a block of half the width (where each launch costs
+            // about half), their Krylov processes restarting from the current
+            // iterates
+            if (feed && next >= feed->total && ctx->opt_narrow && n / 2 >= kNarrowMin) {
+                int nopen = 0;
+                for (int r = 0; r < n; r++) nopen += lane_src[r] >= 0 && !w.h[r].outer_done;
+                if (nopen > 0 && 2 * nopen <= n) {
+                    narrowing = true;
+                    return false;
+                }
+            }
             prepare();
             const VecGeo gh = vgeo(Vv, prec, n);
             void* r = ws_get(ctx, "bi_r", nbp);
@@ -1433,10 +1496,48 @@ static void ru_solve(Work& w, const disco_solver_params& P, int prec, double2* b
         pull(w);
         bool done = true;
         for (auto& s : w.h) done &= s.outer_done != 0;
-        if (!done && !gave_up) {
+        if (!done && !gave_up && !narrowing) {
             fold_in();  // the correction since the last update (zero right after one)
             done = true;
             for (auto& s : w.h) done &= s.outer_done != 0;
+        }
+        if (narrowing && !done) {
+            // the open lanes (the correction is folded in, the finished ones are
+            // handed over) move into lanes 0..m-1 of a block of half the width
+            std::vector<int> keep;
+            for (int r = 0; r < n; r++)
+                if (lane_src[r] >= 0 && !w.h[r].outer_done) keep.push_back(r);
+            const int n2 = n / 2, m = (int)keep.size();
+            for (int q = 0; q < m; q++) hlane[q] = keep[q];
+            HIPCHK(hipMemcpyAsync(dlane, hlane.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+            const size_t nb2 = disco::native_bytes(ctx, DISCO_F64, n2);
+            double2* tmp = (double2*)ws_get(ctx, "ru_narrow", nb2);
+            for (double2* v : {x64, b64}) {
+                hipLaunchKernelGGL(k_lanes_compact, dim3(1024), dim3(256), 0, ctx->stream, v, tmp, V, n, n2, dlane, m);
+                HIPCHK(hipMemcpyAsync(v, tmp, nb2, hipMemcpyDeviceToDevice, ctx->stream));
+            }
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            ws_free(ctx, "ru_narrow");
+            std::vector<int> src2(n2, -1), it2(n2, 0), up2(n2, 0);
+            for (int q = 0; q < m; q++) {
+                // the iterations and updates so far carry over into the lane's statistics
+                src2[q] = lane_src[keep[q]];
+                it2[q] = lane_it0[keep[q]] - iters;
+                up2[q] = lane_up0[keep[q]] - outer;
+            }
+            if (trace)
+                fprintf(stderr, "[disco] %d open lanes move into a block of %d at iteration %d\n", m, n2, iters);
+            n = n2;
+            w = make_work(ctx, n);
+            g64 = vgeo(V, DISCO_F64, n);
+            op.nsb = disco::stencil_nsb(ctx, n, eo);
+            lane_src = src2;
+            lane_it0 = it2;
+            lane_up0 = up2;
+            iters_all += iters;
+            carry = true;
+            carried = m;
+            continue;
         }
         int fb = 0;
         int total = iters;
@@ -1743,19 +1844,6 @@ namespace disco {
 
 // Per-block solver state: scalars, partial sums (up to 4 quantities per
 // right-hand side: the stencil's four-sum epilogue, FGMRES dots), cleared.
-static Work make_work(disco_ctx* ctx, int n) {
-    Work w;
-    w.ctx = ctx;
-    w.n = n;
-    w.V = ctx->V;
-    w.nsb = stencil_nsb(ctx, n);
-    w.sc = (RhsScal*)ws_get(ctx, "sv_scal", sizeof(RhsScal) * n);
-    VecGeo g = vgeo(ctx->V, DISCO_F64, n);
-    size_t slots = (size_t)std::max(std::max(w.nsb, stencil_nsb(ctx, n, true)), g.nb);
-    w.part = (double2*)ws_get(ctx, "sv_part", sizeof(double2) * slots * 4 * n);
-    HIPCHK(hipMemsetAsync(w.sc, 0, sizeof(RhsScal) * n, ctx->stream));
-    return w;
-}
 
 // Every right-hand side of the queue f through a block of (at most) n lanes.
 // BICGSTAB_RU keeps the lanes busy: a converged lane takes the next right-hand

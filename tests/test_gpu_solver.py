@@ -362,3 +362,54 @@ def test_reliable_updates_queue_survives_the_fallback(disco, fallback):
         assert rr.max() < 0.9          # every one was worked on, none returned as x = 0
         assert all(s.fallback_used == 0 for s in st)
         assert all(s.converged == (r <= tol) for s, r in zip(st, rr))
+
+
+@pytest.mark.parametrize("inner", ["F32", "BF16"])
+def test_reliable_updates_narrow_the_tail(disco, capfd, inner):
+    """Forty right-hand sides (two of them zero, one scaled by 1e-3) through a
+    block of 32 lanes: once the queue is empty and at most half of the lanes
+    are open, the open ones move into a block of 16 and go on from their
+    current iterates.  Every solution meets the tolerance by the oracle's FP64
+    residual, the library reports that residual and the iterations each right-
+    hand side took over both blocks, and the solutions agree with a run that
+    keeps the width (a lane mix-up in the move would show at O(1))."""
+    import os
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.124, 1.2
+    U = synth.gauge_field(dims, 0.3, 81)
+    A = oracle.clover(U, dims, kappa, csw)
+    ctx = disco.Context(dims, BC)
+    ctx.gauge_set(U)
+    ctx.clover_setup(kappa, csw)
+    b = synth.random_spinor(ctx.V, 40, 82)
+    b[5] = 0
+    b[39] = 0
+    b[33] *= 1e-3
+    tol = 1e-12 if inner == "F32" else 1e-10
+    live = [k for k in range(40) if k not in (5, 39)]
+    sol = {}
+    for narrow in (1, 0):
+        ctx.set_option(disco.OPT_NARROW, narrow)
+        P = ctx.params(method=disco.BICGSTAB_RU, tol=tol, inner_prec=getattr(disco, inner), rhs_block=32)
+        os.environ["DISCO_TRACE"] = "1"
+        try:
+            x, st = ctx.solve_multi_rhs(ctx.dev(b), P)
+        finally:
+            del os.environ["DISCO_TRACE"]
+        moves = capfd.readouterr().err.count("move into a block of 16")
+        x = x.cpu().numpy()
+        sol[narrow] = x
+        assert np.abs(x[5]).max() == 0 and np.abs(x[39]).max() == 0
+        rr = _true_rel_res(U, A, dims, kappa, b[live], x[live])
+        _say("  narrow=%d %s: %d moves, iterations per rhs %s, oracle residual %.2e" %
+             (narrow, inner, moves, [s.iters for s in st], rr.max()))
+        assert moves == (1 if narrow else 0)
+        assert rr.max() <= tol * 1.05
+        assert all(s.fallback_used == 0 and s.converged for s in st)
+        assert all(st[k].iters > 0 for k in live)
+        for q, k in enumerate(live):
+            assert abs(rr[q] - st[k].true_rel_residual) <= max(1e-2 * rr[q], 2e-15)
+    ctx.set_option(disco.OPT_NARROW, 1)
+    for k in live:
+        d = np.linalg.norm(sol[1][k] - sol[0][k]) / np.linalg.norm(sol[0][k])
+        assert d < 1e4 * tol, (k, d)
