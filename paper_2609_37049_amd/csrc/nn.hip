@@ -575,7 +575,11 @@ struct DwArgs {
 // C[(o,s,a)][(d_local,i,t,b)] += sum over (site, colour) of g[(o,s,a)] phi[(d,i,t,b)],
 // K ordered colour-major (k = colour*64 + site) so that a thread's four sites
 // land in one 8-byte LDS store.
-template <int CI, int CO>
+// GBACK (one output channel, sixteen inputs): the gradient is carried back
+// along the path instead of the inputs forward, sum_x g(x) conj(T_d(x) phi(x+d))
+// = sum_y (T_d(y-d)^+ g(y-d)) conj(phi(y)): one channel transported per site
+// and offset instead of sixteen, and phi read in place.
+template <int CI, int CO, bool GBACK = false>
 __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
     constexpr int NB = 128 / (CI * 8);
     constexpr int MOP = CO * 8 < 16 ? 16 : CO * 8;
@@ -598,6 +602,7 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
 #pragma unroll
         for (int c = 0; c < NCt; c++) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    static_assert(!GBACK || (CO == 1 && CI == 16), "the gradient goes back along the path for 16 -> 1 only");
     const int p = tid & 15, sg = tid >> 4;  // B fill: (d_local, i) pair and group of 4 sites
     const int dl = p / CI, ich = p % CI, d = batch * NB + dl;
     const long total = (long)a.g_.ntile * a.n;
@@ -613,7 +618,18 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
             for (int u = 0; u < 4; u++) {
                 int cs[4];
                 local_coords(sg * 4 + u, org, cs);
-                if (d < kOff) {
+                if (GBACK && d < kOff) {
+                    // phi(y) at the tile's own sites, untransported
+                    const uint4* ip = (const uint4*)(a.act + (((size_t)rhs * a.V + site_of(a.g_, cs)) * CI + ich) * 12);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const uint4 v = ip[k];
+                        ph[u][4 * k] = v.x;
+                        ph[u][4 * k + 1] = v.y;
+                        ph[u][4 * k + 2] = v.z;
+                        ph[u][4 * k + 3] = v.w;
+                    }
+                } else if (d < kOff) {
                     const int s0 = site_of(a.g_, cs);
                     const int ys = shifted_site(a.g_, cs, d, 1);
                     const uint2* tp = a.ttab + ((size_t)d * a.V + s0) * 9;
@@ -650,7 +666,39 @@ __global__ __launch_bounds__(256) void k_nn_dw(const DwArgs a) {
                 }
         }
         // A: gradient rows (o, s, a), K (colour, site)
-        if (CO == 16 || tid < 16) {
+        if constexpr (GBACK) {
+            // one (site, spin) per thread: T_d(y-d)^+ g(y-d), three colours
+            const int sl = tid >> 2, sp = tid & 3;
+            int cs[4];
+            local_coords(sl, org, cs);
+            uint32_t o3[3] = {0u, 0u, 0u};
+            if (d < kOff) {
+                const int z = shifted_site(a.g_, cs, d, -1);
+                const uint2* tp = a.ttab + ((size_t)d * a.V + z) * 9;
+                uint2 T[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) T[k] = tp[k];
+                const uint32_t* gp = a.g + ((size_t)rhs * a.V + z) * 12 + sp * 3;
+                const uint32_t g3[3] = {gp[0], gp[1], gp[2]};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    // row c of T^+: entries T[b][c] conjugated (sign bit of Ti flipped)
+                    float re = 0.f, im = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 3; b++) {
+                        const uint2 t = T[b * 3 + c];
+                        re = dot2(t.x ^ 0x80000000u, g3[b], re);
+                        im = dot2(t.y ^ 0x00008000u, g3[b], im);
+                    }
+                    o3[c] = pk2(re, im);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                sA[(sp * 2) * kLdw + c * 64 + sl] = (uint16_t)(o3[c] & 0xffffu);
+                sA[(sp * 2 + 1) * kLdw + c * 64 + sl] = (uint16_t)(o3[c] >> 16);
+            }
+        } else if (CO == 16 || tid < 16) {
             const int o = CO == 16 ? (tid & 15) : 0;
             const int sgA = CO == 16 ? (tid >> 4) : tid;
             uint32_t raw[4][12];
@@ -1007,7 +1055,8 @@ void dw_launch(disco_net* net, int n, const uint32_t* act, const uint32_t* g, fl
     a.nlogical = nbatch * a.nchunk;
     constexpr int MOP = CO * 8 < 16 ? 16 : CO * 8;
     a.part = (float*)net_ws(net, "dw_part", sizeof(float) * (size_t)nbatch * a.nchunk * MOP * 128);
-    hipLaunchKernelGGL((k_nn_dw<CI, CO>), dim3(xcd_grid(a.nlogical)), dim3(256), 0, net->ctx->stream, a);
+    hipLaunchKernelGGL((k_nn_dw<CI, CO, CO == 1 && CI == 16>), dim3(xcd_grid(a.nlogical)), dim3(256), 0,
+                       net->ctx->stream, a);
     hipLaunchKernelGGL(k_nn_dw_reduce, dim3(gridfor((long)kOff * CO * CI * 16)), dim3(256), 0, net->ctx->stream,
                        a.part, a.nchunk, CI, CO, gw);
 }
