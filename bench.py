@@ -1,6 +1,6 @@
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--method ru|dc]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner bf16|f32] [--method ru|dc] [--inner-tol D]
                     [--workload batch_24x24x24x48|prec_16x16x16x32|prod_32x32x32x64|learned_24x24x24x48]
                     [--nv-per-step N] [--nn-pairs P] [--nn-steps S]
                     [--no-cpu-baseline] [--no-legs]
@@ -333,7 +333,8 @@ def production_subset(args, d, torch, synth):
     ctx = d.Context(dims, pre.bc, 0)
     doms = {"8x8x8x16": ctx.domains(synth.tiling_cuts(dims, (8, 8, 8, 16))),
             "16x16x16x32": ctx.domains(synth.tiling_cuts(dims, (16, 16, 16, 32)))}
-    P = ctx.params(method=d.BICGSTAB_RU, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block)
+    P = ctx.params(method=d.BICGSTAB_RU, tol=1e-10, inner_prec=inner, rhs_block=args.rhs_block,
+                   inner_tol=args.inner_tol or 0.0)
     dev = "cuda:0"
     Vfull = torch.zeros((T, nvs, ctx.Vs, 3), dtype=torch.complex128, device=dev)
     L = {k: torch.zeros((len(loop_codes), 4, T), dtype=torch.complex128, device=dev) for k in ["full"] + list(doms)}
@@ -417,6 +418,7 @@ def production_subset(args, d, torch, synth):
                                   "16^3x32, BiCGStab %s-storage/FP32 inner with FP64 reliable updates to 1e-10"
                                   % (pre.kappa, pre.csw, nv, nvs, args.inner),
                       "lattice": "32x32x32x64", "ensembles": 4, "nv": nv, "nv_used": nvs, "timeslices": tsel,
+                      "inner_tol": args.inner_tol or "library default",
                       "rhs_block": blk, "site_order_tile": list(tile)},
            "rates": {k: {"logical_rhs": logical[k], "solves": packed[k], "seconds": round(secs[k], 2),
                          "logical_rhs_per_s": round(logical[k] / secs[k], 2)} for k in L},
